@@ -1,0 +1,595 @@
+// api.cpp — the C ABI of libbm.so: validation, device memory, the blocked
+// greedy driver, CSR and edge finalisation, result ownership.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bm.h"
+#include "bm_internal.h"
+#include "bounds.h"
+#include "kernels.h"
+
+using namespace bm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct BmError {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string &msg) { throw BmError{code, msg}; }
+
+void hip_ok(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) {
+        if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+            fail(BM_ENOMEM, std::string(what) + ": " + hipGetErrorString(e));
+        fail(BM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+using clk = std::chrono::steady_clock;
+double ms_since(clk::time_point t0) { return std::chrono::duration<double, std::milli>(clk::now() - t0).count(); }
+
+size_t dtype_size(int32_t dtype) { return dtype == BM_F64 ? 8 : dtype == BM_F32 ? 4 : 2; }
+
+int bitlen(uint64_t v) { return v ? 64 - __builtin_clzll(v) : 0; }
+
+// ---- device context: selected device, stream, tracked allocations ------------------------
+struct Device {
+    int dev = 0, prev_dev = -1;
+    hipStream_t s = nullptr;
+    bool own_stream = false;
+    int64_t budget = 0, used = 0;
+    std::vector<std::pair<void *, size_t>> bufs;
+    void *pinned = nullptr;
+
+    explicit Device(const bm_options &o)
+    {
+        int count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) fail(BM_ENODEVICE, "no HIP device is visible");
+        hip_ok(hipGetDevice(&prev_dev), "hipGetDevice");
+        dev = o.device < 0 ? prev_dev : o.device;
+        if (dev >= count) fail(BM_ENODEVICE, "options.device is out of range");
+        hip_ok(hipSetDevice(dev), "hipSetDevice");
+        budget = o.max_device_bytes;
+        if (o.stream) {
+            s = (hipStream_t)o.stream;
+        } else {
+            hip_ok(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
+            own_stream = true;
+        }
+        hip_ok(hipHostMalloc(&pinned, 4096, hipHostMallocDefault), "hipHostMalloc");
+    }
+    ~Device()
+    {
+        if (s) (void)hipStreamSynchronize(s);
+        for (auto &b : bufs) (void)hipFree(b.first);
+        if (pinned) (void)hipHostFree(pinned);
+        if (own_stream && s) (void)hipStreamDestroy(s);
+        if (prev_dev >= 0) (void)hipSetDevice(prev_dev);
+    }
+    Device(const Device &) = delete;
+    Device &operator=(const Device &) = delete;
+
+    void *raw_alloc(size_t bytes, bool tracked)
+    {
+        if (bytes == 0) bytes = 16;
+        if (budget > 0 && used + (int64_t)bytes > budget)
+            fail(BM_ENOMEM, "device memory cap (options.max_device_bytes) exceeded");
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            fail(BM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        used += (int64_t)bytes;
+        if (tracked) bufs.emplace_back(p, bytes);
+        return p;
+    }
+    template <class T> T *alloc(size_t count) { return (T *)raw_alloc(count * sizeof(T), true); }
+    template <class T> T *zeros(size_t count)
+    {
+        T *p = alloc<T>(count);
+        hip_ok(hipMemsetAsync(p, 0, std::max<size_t>(count * sizeof(T), 1), s), "hipMemsetAsync");
+        return p;
+    }
+    void release(void *p)
+    {
+        for (size_t i = 0; i < bufs.size(); ++i)
+            if (bufs[i].first == p) {
+                (void)hipFree(p);
+                used -= (int64_t)bufs[i].second;
+                bufs.erase(bufs.begin() + (long)i);
+                return;
+            }
+    }
+    // stop tracking (ownership moves to a result)
+    void detach(void *p)
+    {
+        for (size_t i = 0; i < bufs.size(); ++i)
+            if (bufs[i].first == p) {
+                bufs.erase(bufs.begin() + (long)i);
+                return;
+            }
+    }
+    void sync() { hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"); }
+    template <class T> T fetch(const T *dptr)
+    {
+        hip_ok(hipMemcpyAsync(pinned, dptr, sizeof(T), hipMemcpyDeviceToHost, s), "hipMemcpyAsync D2H");
+        sync();
+        T v;
+        std::memcpy(&v, pinned, sizeof(T));
+        return v;
+    }
+};
+
+// ---- argument checks that need no device ----------------------------------------------
+void check_common(const void *points, int64_t n, int32_t d, int32_t dtype, double eps, const bm_options &o)
+{
+    if (n < 0) fail(BM_EINVAL, "n must be >= 0");
+    if (n > INT32_MAX) fail(BM_EINVAL, "n must be <= INT32_MAX");
+    if (d < 1) fail(BM_EINVAL, "d must be >= 1");
+    if (dtype != BM_F64 && dtype != BM_F32 && dtype != BM_F16) fail(BM_EINVAL, "unknown dtype");
+    if (!std::isfinite(eps) || !(eps > 0.0)) fail(BM_EINVAL, "eps must be finite and > 0");
+    if (!(eps * eps > 0.0)) fail(BM_EINVAL, "eps*eps underflows to 0 in FP64");
+    if (n > 0 && !points) fail(BM_EINVAL, "points is NULL");
+    if (o.path < BM_PATH_AUTO || o.path > BM_PATH_F16) fail(BM_EINVAL, "unknown path");
+    if (o.refine != 0 && o.refine != 1) fail(BM_EINVAL, "refine must be 0 or 1");
+    if (o.block < 0 || o.block > 4096) fail(BM_EINVAL, "block must be 0 (automatic) or 1..4096");
+    if (o.max_device_bytes < 0 || o.init_member_capacity < 0) fail(BM_EINVAL, "negative size option");
+    if (o.path == BM_PATH_F16 && dtype != BM_F16) fail(BM_EINVAL, "path F16 needs float16 storage");
+}
+
+bool host_all_finite(const void *points, int64_t count, int32_t dtype)
+{
+    if (dtype == BM_F64) {
+        const double *p = (const double *)points;
+        for (int64_t i = 0; i < count; ++i)
+            if (!std::isfinite(p[i])) return false;
+    } else if (dtype == BM_F32) {
+        const float *p = (const float *)points;
+        for (int64_t i = 0; i < count; ++i)
+            if (!std::isfinite(p[i])) return false;
+    } else {
+        const uint16_t *p = (const uint16_t *)points;
+        for (int64_t i = 0; i < count; ++i)
+            if ((p[i] & 0x7c00u) == 0x7c00u) return false;
+    }
+    return true;
+}
+
+std::vector<int32_t> check_order(const int64_t *order, int64_t n)
+{
+    std::vector<int32_t> perm;
+    if (!order) return perm;
+    std::vector<uint8_t> seen((size_t)n, 0);
+    perm.resize((size_t)n);
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t p = order[r];
+        if (p < 0 || p >= n || seen[(size_t)p]) fail(BM_EINVAL, "order is not a permutation of 0..n-1");
+        seen[(size_t)p] = 1;
+        perm[(size_t)r] = (int32_t)p;
+    }
+    return perm;
+}
+
+bm_result *new_result()
+{
+    bm_result *r = (bm_result *)std::calloc(1, sizeof(bm_result));
+    if (!r) fail(BM_ENOMEM, "host allocation failed");
+    return r;
+}
+
+// ---- one build ------------------------------------------------------------------------
+struct Job {
+    const void *points;
+    int64_t n;
+    int32_t d, dtype;
+    double eps;
+    const int64_t *order;          // greedy order (ignored in fixed mode)
+    const int32_t *fixed;          // fixed landmark list (original indices) or null
+    int64_t n_fixed;
+};
+
+int auto_block(int64_t n)
+{
+    if (n >= (1 << 17)) return 1024;
+    if (n >= (1 << 13)) return 256;
+    return 64;
+}
+
+bm_result *run_job(const Job &job, const bm_options &o)
+{
+    const auto t_start = clk::now();
+    const int64_t n = job.n;
+    const int32_t d = job.d;
+    bm_result *res = new_result();
+    res->stats.path = o.path;
+    try {
+        Device dev(o);
+        res->device = dev.dev;
+        const double e2 = job.eps * job.eps;   // RN(eps^2), once, in FP64
+        const auto t_prep = clk::now();
+
+        // -- stored points on the device
+        const void *Xd = job.points;
+        if (!o.points_on_device && n > 0) {
+            void *p = dev.raw_alloc((size_t)n * d * dtype_size(job.dtype), true);
+            hip_ok(hipMemcpyAsync(p, job.points, (size_t)n * d * dtype_size(job.dtype), hipMemcpyHostToDevice, dev.s),
+                   "upload points");
+            Xd = p;
+        }
+        std::vector<int32_t> perm_h = job.fixed ? std::vector<int32_t>() : check_order(job.order, n);
+        int32_t *perm_d = nullptr;
+        if (!perm_h.empty()) {
+            perm_d = dev.alloc<int32_t>((size_t)n);
+            hip_ok(hipMemcpyAsync(perm_d, perm_h.data(), (size_t)n * 4, hipMemcpyHostToDevice, dev.s), "upload order");
+        }
+        PointsView P{Xd, n, d, job.dtype, perm_d};
+
+        // -- validation and statistics on the device
+        int32_t path = o.path;
+        double max_nu = 0.0, max_abs = 0.0;
+        double *nu = nullptr;
+        if (n > 0) {
+            if (o.points_on_device) {
+                int *bad = dev.zeros<int>(1);
+                hip_ok(launch_check_finite(Xd, job.dtype, n * (int64_t)d, bad, dev.s), "check_finite");
+                if (dev.fetch(bad)) fail(BM_ENONFINITE, "a coordinate is NaN or infinite");
+            }
+            nu = dev.alloc<double>((size_t)n);
+            unsigned long long *st2 = dev.zeros<unsigned long long>(2);
+            hip_ok(launch_point_stats(P, nu, st2, dev.s), "point_stats");
+            hip_ok(hipMemcpyAsync(dev.pinned, st2, 16, hipMemcpyDeviceToHost, dev.s), "stats D2H");
+            dev.sync();
+            unsigned long long raw[2];
+            std::memcpy(raw, dev.pinned, 16);
+            std::memcpy(&max_nu, &raw[0], 8);
+            std::memcpy(&max_abs, &raw[1], 8);
+        }
+        if (path == BM_PATH_AUTO) path = BM_PATH_FP32;   // MFMA paths are selected explicitly for now
+        res->stats.path = path;
+
+        // -- path preparation
+        Fp32Thresholds thr32{};
+        float *xf = nullptr;
+        if (path == BM_PATH_FP32) {
+            thr32 = fp32_thresholds(e2, d, job.dtype, std::sqrt(max_nu), max_abs);
+            if (job.dtype == BM_F32 && !perm_d) {
+                xf = (float *)Xd;
+            } else if (n > 0) {
+                xf = dev.alloc<float>((size_t)n * d);
+                hip_ok(launch_to_f32(P, xf, dev.s), "to_f32");
+            }
+        } else {
+            fail(BM_EINVAL, "this path is not available in this build");
+        }
+        res->stats.ms_prepare = ms_since(t_prep);
+
+        // -- range passes
+        const auto t_greedy = clk::now();
+        const int B = o.block ? o.block : auto_block(n);
+        res->stats.block = B;
+        const int32_t bn = std::max(1, bitlen((uint64_t)std::max<int64_t>(n - 1, 1)));
+        unsigned long long cap = o.init_member_capacity
+                                     ? (unsigned long long)o.init_member_capacity
+                                     : (unsigned long long)std::max<int64_t>(2 * n, 1 << 16);
+        uint64_t *keys = dev.alloc<uint64_t>(cap);
+        GreedyState *st = dev.zeros<GreedyState>(1);
+        int32_t *lm_d = dev.alloc<int32_t>((size_t)std::max<int64_t>(job.fixed ? job.n_fixed : n, 1));
+        int32_t *A = dev.alloc<int32_t>((size_t)B);
+        GreedyState hs{};
+        int64_t L = 0;
+        RangeOut ro{nullptr, keys, cap, st, bn};
+
+        auto run_range = [&](int64_t ord0, const int32_t *na_dev) {
+            ro.keys = keys;
+            ro.cap = cap;
+            hip_ok(launch_range_fp32(xf, P, e2, thr32, o.refine, A, na_dev, B, ord0, ro, dev.s), "range_fp32");
+        };
+        // grow the key buffer if the last block overflowed it, then redo that block's
+        // range pass (covered bits are idempotent ORs, so only the keys change)
+        auto regrow_if_needed = [&](unsigned long long before, int64_t ord0, const int32_t *na_dev) {
+            hs = dev.fetch(st);
+            if (hs.nkeys <= cap) return;
+            unsigned long long ncap = std::max<unsigned long long>(2 * cap, hs.nkeys + hs.nkeys / 2);
+            uint64_t *nk = dev.alloc<uint64_t>(ncap);
+            if (before) hip_ok(hipMemcpyAsync(nk, keys, before * 8, hipMemcpyDeviceToDevice, dev.s), "regrow copy");
+            dev.release(keys);
+            keys = nk;
+            cap = ncap;
+            hip_ok(hipMemcpyAsync(&st->nkeys, &before, 8, hipMemcpyHostToDevice, dev.s), "reset nkeys");
+            run_range(ord0, na_dev);
+            hs = dev.fetch(st);
+            if (hs.nkeys > cap) fail(BM_EINTERNAL, "membership count changed on recompute");
+        };
+
+        if (job.fixed) {
+            // fixed-landmark mode: landmarks given as original indices (identity order)
+            L = job.n_fixed;
+            if (L > 0) hip_ok(hipMemcpyAsync(lm_d, job.fixed, (size_t)L * 4, hipMemcpyHostToDevice, dev.s), "upload lm");
+            int32_t *na_d = dev.alloc<int32_t>(1);
+            for (int64_t a0 = 0; a0 < L; a0 += B) {
+                const int32_t na = (int32_t)std::min<int64_t>(B, L - a0);
+                hip_ok(hipMemcpyAsync(A, job.fixed + a0, (size_t)na * 4, hipMemcpyHostToDevice, dev.s), "upload A");
+                hip_ok(hipMemcpyAsync(na_d, &na, 4, hipMemcpyHostToDevice, dev.s), "upload na");
+                const unsigned long long before = hs.nkeys;
+                run_range(a0, na_d);
+                regrow_if_needed(before, a0, na_d);
+                res->stats.pairs_issued += (int64_t)na * n;
+                res->stats.blocks++;
+            }
+        } else if (n > 0) {
+            const int nw = (B + 63) / 64;
+            uint64_t *covered = dev.zeros<uint64_t>((size_t)((n + 63) / 64));
+            int32_t *cand = dev.alloc<int32_t>((size_t)B);
+            uint64_t *C = dev.alloc<uint64_t>((size_t)B * nw);
+            ro.covered = covered;
+            for (;;) {
+                const unsigned long long before = hs.nkeys;
+                hip_ok(launch_gather(covered, n, st, B, cand, dev.s), "gather");
+                hip_ok(launch_resolve_exact(P, e2, cand, st, B, C, dev.s), "resolve");
+                hip_ok(launch_accept(C, cand, st, B, A, lm_d + L, perm_d, dev.s), "accept");
+                run_range(L, &st->na);
+                regrow_if_needed(before, L, &st->na);
+                if (hs.nc == 0) break;
+                res->stats.blocks++;
+                res->stats.candidates += hs.nc;
+                res->stats.pairs_issued += (int64_t)hs.nc * (hs.nc - 1) / 2 + (int64_t)hs.na * n;
+                L += hs.na;
+                if (hs.cursor >= n && hs.nc < B) {
+                    // the gather reached the end; one more gather would find nothing
+                    break;
+                }
+            }
+        }
+        dev.sync();
+        res->stats.band_pairs = (int64_t)hs.band;
+        res->stats.pairs_useful = L * n;
+        res->stats.ms_greedy = ms_since(t_greedy);
+
+        // -- membership CSR
+        const auto t_csr = clk::now();
+        const int64_t M = (int64_t)hs.nkeys;
+        int64_t *row_ptr = dev.alloc<int64_t>((size_t)L + 1);
+        int32_t *midx = dev.alloc<int32_t>((size_t)std::max<int64_t>(M, 1));
+        uint64_t *skeys = dev.alloc<uint64_t>((size_t)std::max<int64_t>(M, 1));
+        const int end_bit = bn + std::max(1, bitlen((uint64_t)L));
+        if (M > 0) {
+            size_t tb = 0;
+            hip_ok(sort_keys(nullptr, &tb, keys, skeys, (size_t)M, end_bit, dev.s), "sort size");
+            void *tmp = dev.raw_alloc(tb, true);
+            hip_ok(sort_keys(tmp, &tb, keys, skeys, (size_t)M, end_bit, dev.s), "sort");
+            dev.release(tmp);
+        }
+        hip_ok(launch_csr_from_sorted(skeys, M, L, bn, row_ptr, midx, dev.s), "csr");
+        dev.release(keys);
+        keys = nullptr;
+        dev.sync();
+        res->stats.ms_csr = ms_since(t_csr);
+
+        // -- edges
+        const auto t_edges = clk::now();
+        int64_t E = 0;
+        int32_t *edges = nullptr;
+        if (L > 1 && M > 0) {
+            int64_t *cnt = dev.zeros<int64_t>((size_t)n);
+            hip_ok(launch_point_degree(midx, M, cnt, dev.s), "point_degree");
+            int64_t *sptr = dev.alloc<int64_t>((size_t)n + 1);
+            size_t tb = 0;
+            hip_ok(scan_excl_i64(nullptr, &tb, cnt, sptr, (size_t)n, dev.s), "scan size");
+            void *tmp = dev.raw_alloc(std::max<size_t>(tb, (size_t)(L + 1) * 0 + 16), true);
+            hip_ok(scan_excl_i64(tmp, &tb, cnt, sptr, (size_t)n, dev.s), "scan");
+            dev.release(tmp);
+            int32_t *slist = dev.alloc<int32_t>((size_t)M);
+            hip_ok(hipMemsetAsync(cnt, 0, (size_t)n * 8, dev.s), "zero fill");
+            hip_ok(launch_fill_slists(skeys, M, bn, sptr, cnt, slist, dev.s), "fill_slists");
+            dev.release(cnt);
+            int64_t *deg = dev.alloc<int64_t>((size_t)L);
+            hip_ok(launch_edge_pass(0, L, row_ptr, midx, sptr, slist, deg, nullptr, nullptr, dev.s), "edge count");
+            int64_t *eptr = dev.alloc<int64_t>((size_t)L + 1);
+            tb = 0;
+            hip_ok(scan_excl_i64(nullptr, &tb, deg, eptr, (size_t)L, dev.s), "scan size");
+            tmp = dev.raw_alloc(tb, true);
+            hip_ok(scan_excl_i64(tmp, &tb, deg, eptr, (size_t)L, dev.s), "scan");
+            dev.release(tmp);
+            E = dev.fetch(eptr + L);
+            edges = dev.alloc<int32_t>((size_t)std::max<int64_t>(2 * E, 1));
+            if (E > 0)
+                hip_ok(launch_edge_pass(1, L, row_ptr, midx, sptr, slist, deg, eptr, edges, dev.s), "edge emit");
+            dev.sync();
+        }
+        res->stats.ms_edges = ms_since(t_edges);
+
+        // -- hand over
+        const auto t_dl = clk::now();
+        res->n_landmarks = L;
+        res->n_edges = E;
+        if (o.results_on_device) {
+            if (!edges) edges = dev.alloc<int32_t>(1);
+            res->landmarks = lm_d;
+            res->member_ptr = row_ptr;
+            res->member_idx = midx;
+            res->edges = edges;
+            res->on_device = 1;
+            dev.detach(lm_d);
+            dev.detach(row_ptr);
+            dev.detach(midx);
+            dev.detach(edges);
+        } else {
+            res->landmarks = (int32_t *)std::malloc((size_t)std::max<int64_t>(L, 1) * 4);
+            res->member_ptr = (int64_t *)std::malloc((size_t)(L + 1) * 8);
+            res->member_idx = (int32_t *)std::malloc((size_t)std::max<int64_t>(M, 1) * 4);
+            res->edges = (int32_t *)std::malloc((size_t)std::max<int64_t>(2 * E, 1) * 4);
+            if (!res->landmarks || !res->member_ptr || !res->member_idx || !res->edges)
+                fail(BM_ENOMEM, "host allocation of the result failed");
+            if (L) hip_ok(hipMemcpyAsync(res->landmarks, lm_d, (size_t)L * 4, hipMemcpyDeviceToHost, dev.s), "D2H");
+            hip_ok(hipMemcpyAsync(res->member_ptr, row_ptr, (size_t)(L + 1) * 8, hipMemcpyDeviceToHost, dev.s), "D2H");
+            if (M) hip_ok(hipMemcpyAsync(res->member_idx, midx, (size_t)M * 4, hipMemcpyDeviceToHost, dev.s), "D2H");
+            if (E) hip_ok(hipMemcpyAsync(res->edges, edges, (size_t)E * 8, hipMemcpyDeviceToHost, dev.s), "D2H");
+            dev.sync();
+        }
+        res->stats.ms_download = ms_since(t_dl);
+        res->stats.ms_total = ms_since(t_start);
+        return res;
+    } catch (...) {
+        bm_result_free(res);
+        throw;
+    }
+}
+
+template <class F> int guarded(F &&f)
+{
+    try {
+        g_last_error.clear();
+        return f();
+    } catch (const BmError &e) {
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return BM_ENOMEM;
+    } catch (...) {
+        g_last_error = "unexpected internal error";
+        return BM_EINTERNAL;
+    }
+}
+
+bm_options resolve_options(const bm_options *opt)
+{
+    bm_options o;
+    bm_default_options(&o);
+    if (opt) o = *opt;
+    return o;
+}
+
+} // namespace
+
+extern "C" {
+
+int bm_default_options(bm_options *opt)
+{
+    if (!opt) return BM_EINVAL;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->path = BM_PATH_AUTO;
+    opt->refine = 1;
+    opt->device = -1;
+    return BM_OK;
+}
+
+int bm_build(const void *points, int64_t n, int32_t d, int32_t dtype, double eps, const int64_t *order,
+             const bm_options *opt, bm_result **out)
+{
+    return guarded([&]() -> int {
+        if (!out) fail(BM_EINVAL, "out is NULL");
+        *out = nullptr;
+        const bm_options o = resolve_options(opt);
+        check_common(points, n, d, dtype, eps, o);
+        if (order) (void)check_order(order, n);
+        if (!o.points_on_device && n > 0 && !host_all_finite(points, n * (int64_t)d, dtype))
+            fail(BM_ENONFINITE, "a coordinate is NaN or infinite");
+        Job job{points, n, d, dtype, eps, order, nullptr, 0};
+        *out = run_job(job, o);
+        return BM_OK;
+    });
+}
+
+int bm_range_sets(const void *points, int64_t n, int32_t d, int32_t dtype, double eps, const int32_t *landmarks,
+                  int64_t n_landmarks, const bm_options *opt, bm_result **out)
+{
+    return guarded([&]() -> int {
+        if (!out) fail(BM_EINVAL, "out is NULL");
+        *out = nullptr;
+        const bm_options o = resolve_options(opt);
+        check_common(points, n, d, dtype, eps, o);
+        if (n_landmarks < 0 || (n_landmarks > 0 && !landmarks)) fail(BM_EINVAL, "bad landmark list");
+        for (int64_t i = 0; i < n_landmarks; ++i)
+            if (landmarks[i] < 0 || landmarks[i] >= n) fail(BM_EINVAL, "landmark index out of range");
+        if (!o.points_on_device && n > 0 && !host_all_finite(points, n * (int64_t)d, dtype))
+            fail(BM_ENONFINITE, "a coordinate is NaN or infinite");
+        Job job{points, n, d, dtype, eps, nullptr, landmarks, n_landmarks};
+        *out = run_job(job, o);
+        return BM_OK;
+    });
+}
+
+int bm_build_many(const bm_problem *probs, int32_t n_probs, const bm_options *opt, bm_result **outs)
+{
+    int64_t slots = 0;
+    int rc = guarded([&]() -> int {
+        if (n_probs < 0 || (n_probs > 0 && (!probs || !outs))) fail(BM_EINVAL, "bad problem list");
+        const bm_options o = resolve_options(opt);
+        for (int32_t p = 0; p < n_probs; ++p) {
+            const bm_problem &pr = probs[p];
+            if (pr.n_eps < 0 || (pr.n_eps > 0 && !pr.eps)) fail(BM_EINVAL, "bad eps list");
+            for (int32_t e = 0; e < pr.n_eps; ++e) {
+                check_common(pr.points, pr.n, pr.d, pr.dtype, pr.eps[e], o);
+                outs[slots++] = nullptr;
+            }
+            if (pr.order) (void)check_order(pr.order, pr.n);
+            if (!o.points_on_device && pr.n > 0 && !host_all_finite(pr.points, pr.n * (int64_t)pr.d, pr.dtype))
+                fail(BM_ENONFINITE, "a coordinate is NaN or infinite");
+        }
+        int64_t k = 0;
+        for (int32_t p = 0; p < n_probs; ++p) {
+            const bm_problem &pr = probs[p];
+            for (int32_t e = 0; e < pr.n_eps; ++e) {
+                Job job{pr.points, pr.n, pr.d, pr.dtype, pr.eps[e], pr.order, nullptr, 0};
+                outs[k++] = run_job(job, o);
+            }
+        }
+        return BM_OK;
+    });
+    if (rc != BM_OK && outs)
+        for (int64_t k = 0; k < slots; ++k) {
+            bm_result_free(outs[k]);
+            outs[k] = nullptr;
+        }
+    return rc;
+}
+
+void bm_result_free(bm_result *r)
+{
+    if (!r) return;
+    if (r->on_device) {
+        int prev = -1;
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(r->device);
+        (void)hipFree(r->landmarks);
+        (void)hipFree(r->member_ptr);
+        (void)hipFree(r->member_idx);
+        (void)hipFree(r->edges);
+        if (prev >= 0) (void)hipSetDevice(prev);
+    } else {
+        std::free(r->landmarks);
+        std::free(r->member_ptr);
+        std::free(r->member_idx);
+        std::free(r->edges);
+    }
+    std::free(r);
+}
+
+const char *bm_last_error(void) { return g_last_error.c_str(); }
+
+int bm_device_count(void)
+{
+    int c = 0;
+    if (hipGetDeviceCount(&c) != hipSuccess) return 0;
+    return c;
+}
+
+int bm_abi_version(void) { return BM_ABI_VERSION; }
+
+} // extern "C"

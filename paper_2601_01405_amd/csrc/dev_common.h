@@ -1,0 +1,116 @@
+// dev_common.h — device helpers for the gfx950 kernels (wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bm_internal.h"
+
+namespace bm {
+
+// ---- exact widening of a stored coordinate -------------------------------------------
+template <int DT>
+__device__ __forceinline__ double load_coord(const void *X, int64_t off)
+{
+    if constexpr (DT == 0) return ((const double *)X)[off];
+    else if constexpr (DT == 1) return (double)((const float *)X)[off];
+    else return (double)(float)((const _Float16 *)X)[off];   // binary16 -> f32 -> f64, exact
+}
+
+__device__ __forceinline__ int64_t orig_index(const PointsView &P, int64_t rank)
+{
+    return P.perm ? (int64_t)P.perm[rank] : rank;
+}
+
+// ---- the FP64 predicate --------------------------------------------------------------
+// s(a,b) = sum over k of RN(RN(a_k - b_k)^2), added left to right with round to
+// nearest and no fused multiply-add; member iff s < e2 = RN(eps^2).  Once the
+// partial sum reaches e2 the loop stops: every term is >= 0 and rounded addition
+// is monotone, so the full sum would not be below e2 either.
+template <int DT>
+__device__ __attribute__((noinline)) bool exact_member_t(const void *X, int32_t d, int64_t a, int64_t b,
+                                                         double e2)
+{
+#pragma clang fp contract(off)
+    const int64_t oa = a * (int64_t)d, ob = b * (int64_t)d;
+    double acc = 0.0;
+    for (int32_t k = 0; k < d; ++k) {
+        double t = load_coord<DT>(X, oa + k) - load_coord<DT>(X, ob + k);
+        double sq = t * t;
+        acc = acc + sq;
+        if (acc >= e2) return false;
+    }
+    return acc < e2;
+}
+
+// a, b: ORIGINAL row indices.
+__device__ __forceinline__ bool exact_member(const PointsView &P, int64_t a, int64_t b, double e2)
+{
+    if (P.dtype == 0) return exact_member_t<0>(P.X, P.d, a, b, e2);
+    if (P.dtype == 1) return exact_member_t<1>(P.X, P.d, a, b, e2);
+    return exact_member_t<2>(P.X, P.d, a, b, e2);
+}
+
+// ---- wave64 helpers ------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+__device__ __forceinline__ int mbcnt(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Wave-aggregated append: every lane with `want` gets a distinct slot; one atomic per wave.
+__device__ __forceinline__ unsigned long long wave_append(unsigned long long *counter, bool want,
+                                                          uint64_t *ballot_out = nullptr)
+{
+    uint64_t m = __ballot(want);
+    if (ballot_out) *ballot_out = m;
+    if (!m) return 0;
+    int leader = __ffsll((unsigned long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane_id() == leader) base = atomicAdd(counter, (unsigned long long)__popcll(m));
+    base = __shfl(base, leader, 64);
+    return base + (unsigned long long)mbcnt(m);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T x)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// Exclusive scan over a whole workgroup of BLOCK threads. `sh` holds BLOCK/64 values.
+template <int BLOCK, typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T *total, T *sh)
+{
+    constexpr int NW = BLOCK / 64;
+    const int lane = lane_id(), wid = (int)(threadIdx.x >> 6);
+    T x = wave_incl_scan(v);
+    if (lane == 63) sh[wid] = x;
+    __syncthreads();
+    if (wid == 0) {
+        T s = lane < NW ? sh[lane] : T(0);
+        s = wave_incl_scan(s);
+        if (lane < NW) sh[lane] = s;
+    }
+    __syncthreads();
+    T off = wid ? sh[wid - 1] : T(0);
+    *total = sh[NW - 1];
+    __syncthreads();
+    return off + x - v;
+}
+
+} // namespace bm

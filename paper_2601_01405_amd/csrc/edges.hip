@@ -1,0 +1,232 @@
+// edges.hip — edges of the Ball Mapper graph, the 1-skeleton of the nerve
+// (Sec. 2.1): (i, j) with i < j whenever the balls of landmarks i and j share a
+// data point.
+//
+// Built through the transpose of the membership CSR: S(x) lists the landmarks
+// whose ball holds x, and the neighbours j > i of landmark i are the union of
+// S(x) over x in its ball.  One workgroup per landmark deduplicates that union
+// either by sorting it in LDS (small unions) or with an LDS bitmap over the
+// range of j (large unions).  Rows come out in landmark order and each row in
+// increasing j, so the list is lexicographic without a global sort.
+#include <climits>
+#include <cstring>
+#include <rocprim/device/device_scan.hpp>
+
+#include "dev_common.h"
+#include "kernels.h"
+
+namespace bm {
+
+__global__ void k_zero_i64(int64_t *p, int64_t count)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// out[0] = 0, out[1 + i] = in[0] + ... + in[i]  (count + 1 outputs)
+hipError_t scan_excl_i64(void *tmp, size_t *tmp_bytes, const int64_t *in, int64_t *out, size_t count, hipStream_t s)
+{
+    size_t bytes = *tmp_bytes;
+    hipError_t e;
+    if (count == 0) {
+        e = hipSuccess;
+        bytes = bytes ? bytes : 16;
+    } else {
+        e = rocprim::inclusive_scan(tmp, bytes, in, out + 1, count, rocprim::plus<int64_t>(), s);
+    }
+    if (tmp != nullptr && e == hipSuccess) {
+        k_zero_i64<<<1, 64, 0, s>>>(out, 1);
+        e = hipGetLastError();
+    }
+    *tmp_bytes = bytes;
+    return e;
+}
+
+__global__ void k_point_degree(const int32_t *member_idx, int64_t M, int64_t *cnt)
+{
+    for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < M; m += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd((unsigned long long *)&cnt[member_idx[m]], 1ull);
+}
+
+hipError_t launch_point_degree(const int32_t *member_idx, int64_t M, int64_t *cnt, hipStream_t s)
+{
+    if (M <= 0) return hipSuccess;
+    int64_t blocks = (M + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    k_point_degree<<<(int)blocks, 256, 0, s>>>(member_idx, M, cnt);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_slists(const uint64_t *keys, int64_t M, int32_t bn, const int64_t *sptr, int64_t *sfill,
+                              int32_t *slist)
+{
+    const uint64_t mask = (1ull << bn) - 1;
+    for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < M; m += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = keys[m];
+        const int64_t x = (int64_t)(k & mask);
+        const int32_t i = (int32_t)(k >> bn);
+        const int64_t pos = sptr[x] + (int64_t)atomicAdd((unsigned long long *)&sfill[x], 1ull);
+        slist[pos] = i;
+    }
+}
+
+hipError_t launch_fill_slists(const uint64_t *keys, int64_t M, int32_t bn, const int64_t *sptr, int64_t *sfill,
+                              int32_t *slist, hipStream_t s)
+{
+    if (M <= 0) return hipSuccess;
+    int64_t blocks = (M + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    k_fill_slists<<<(int)blocks, 256, 0, s>>>(keys, M, bn, sptr, sfill, slist);
+    return hipGetLastError();
+}
+
+constexpr int EP_THREADS = 256;
+constexpr int EP_CAP = 2048;                    // union sizes sorted in LDS
+constexpr int EP_WORDS = 4096;                  // bitmap words per chunk (262144 landmarks, 32 KB)
+
+__global__ __launch_bounds__(EP_THREADS) void k_edge_pass(int mode, const int64_t *row_ptr,
+                                                          const int32_t *member_idx, const int64_t *sptr,
+                                                          const int32_t *slist, int64_t *deg,
+                                                          const int64_t *eptr, int32_t *edges)
+{
+    __shared__ int32_t buf[EP_CAP];
+    __shared__ unsigned long long bits[EP_WORDS];
+    __shared__ int sh_cnt, sh_min, sh_max;
+    __shared__ int64_t sh_scan[EP_THREADS / 64];
+    const int32_t i = (int32_t)blockIdx.x;
+    const int64_t m0 = row_ptr[i], m1 = row_ptr[i + 1];
+    if (threadIdx.x == 0) {
+        sh_cnt = 0;
+        sh_min = INT_MAX;
+        sh_max = -1;
+    }
+    __syncthreads();
+    // pass 1: size and range of the union (with repeats)
+    {
+        int c = 0, mn = INT_MAX, mx = -1;
+        for (int64_t m = m0 + threadIdx.x; m < m1; m += EP_THREADS) {
+            const int32_t x = member_idx[m];
+            for (int64_t q = sptr[x]; q < sptr[x + 1]; ++q) {
+                const int32_t j = slist[q];
+                if (j > i) {
+                    ++c;
+                    mn = min(mn, j);
+                    mx = max(mx, j);
+                }
+            }
+        }
+        if (c) {
+            atomicAdd(&sh_cnt, c);
+            atomicMin(&sh_min, mn);
+            atomicMax(&sh_max, mx);
+        }
+    }
+    __syncthreads();
+    const int total = sh_cnt;
+    const int64_t out0 = (mode == 1) ? eptr[i] : 0;
+    if (total == 0) {
+        if (mode == 0 && threadIdx.x == 0) deg[i] = 0;
+        return;
+    }
+    if (total <= EP_CAP) {
+        // gather, bitonic sort, keep first of each run
+        if (threadIdx.x == 0) sh_cnt = 0;
+        __syncthreads();
+        for (int64_t m = m0 + threadIdx.x; m < m1; m += EP_THREADS) {
+            const int32_t x = member_idx[m];
+            for (int64_t q = sptr[x]; q < sptr[x + 1]; ++q) {
+                const int32_t j = slist[q];
+                if (j > i) buf[atomicAdd(&sh_cnt, 1)] = j;
+            }
+        }
+        int P2 = 2;
+        while (P2 < total) P2 <<= 1;
+        for (int t = total + threadIdx.x; t < P2; t += EP_THREADS) buf[t] = INT_MAX;
+        __syncthreads();
+        for (int k = 2; k <= P2; k <<= 1) {
+            for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                for (int t = threadIdx.x; t < P2; t += EP_THREADS) {
+                    const int u = t ^ jj;
+                    if (u > t) {
+                        const int32_t a = buf[t], b = buf[u];
+                        const bool up = (t & k) == 0;
+                        if ((a > b) == up) {
+                            buf[t] = b;
+                            buf[u] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        // each thread owns a contiguous slice so positions follow the sorted order
+        const int per = (total + EP_THREADS - 1) / EP_THREADS;
+        const int t0 = threadIdx.x * per;
+        int64_t mine = 0;
+        for (int t = t0; t < t0 + per && t < total; ++t) mine += (t == 0 || buf[t] != buf[t - 1]);
+        int64_t uniq;
+        int64_t pos = block_excl_scan<EP_THREADS>(mine, &uniq, sh_scan);
+        if (mode == 0) {
+            if (threadIdx.x == 0) deg[i] = uniq;
+        } else {
+            for (int t = t0; t < t0 + per && t < total; ++t) {
+                if (t == 0 || buf[t] != buf[t - 1]) {
+                    edges[2 * (out0 + pos)] = i;
+                    edges[2 * (out0 + pos) + 1] = buf[t];
+                    ++pos;
+                }
+            }
+        }
+        return;
+    }
+    // bitmap over [jmin, jmax] in chunks of EP_WORDS * 64 landmarks
+    const int jmin = sh_min, jmax = sh_max;
+    int64_t written = 0;
+    for (int64_t base = jmin; base <= jmax; base += (int64_t)EP_WORDS * 64) {
+        const int64_t span = min((int64_t)EP_WORDS * 64, (int64_t)jmax - base + 1);
+        const int nwords = (int)((span + 63) >> 6);
+        for (int t = threadIdx.x; t < nwords; t += EP_THREADS) bits[t] = 0ull;
+        __syncthreads();
+        for (int64_t m = m0 + threadIdx.x; m < m1; m += EP_THREADS) {
+            const int32_t x = member_idx[m];
+            for (int64_t q = sptr[x]; q < sptr[x + 1]; ++q) {
+                const int64_t j = slist[q];
+                if (j > i && j >= base && j < base + span)
+                    atomicOr(&bits[(j - base) >> 6], 1ull << ((j - base) & 63));
+            }
+        }
+        __syncthreads();
+        const int per = (nwords + EP_THREADS - 1) / EP_THREADS;
+        const int w0 = threadIdx.x * per;
+        int64_t mine = 0;
+        for (int w = w0; w < w0 + per && w < nwords; ++w) mine += __popcll(bits[w]);
+        int64_t chunk_total;
+        int64_t pos = block_excl_scan<EP_THREADS>(mine, &chunk_total, sh_scan);
+        if (mode == 1) {
+            for (int w = w0; w < w0 + per && w < nwords; ++w) {
+                unsigned long long b = bits[w];
+                while (b) {
+                    const int bit = __ffsll(b) - 1;
+                    b &= b - 1;
+                    edges[2 * (out0 + written + pos)] = i;
+                    edges[2 * (out0 + written + pos) + 1] = (int32_t)(base + (w << 6) + bit);
+                    ++pos;
+                }
+            }
+        }
+        written += chunk_total;
+        __syncthreads();
+    }
+    if (mode == 0 && threadIdx.x == 0) deg[i] = written;
+}
+
+hipError_t launch_edge_pass(int mode, int64_t L, const int64_t *row_ptr, const int32_t *member_idx,
+                            const int64_t *sptr, const int32_t *slist, int64_t *deg, const int64_t *eptr,
+                            int32_t *edges, hipStream_t s)
+{
+    if (L <= 0) return hipSuccess;
+    k_edge_pass<<<(unsigned)L, EP_THREADS, 0, s>>>(mode, row_ptr, member_idx, sptr, slist, deg, eptr, edges);
+    return hipGetLastError();
+}
+
+} // namespace bm

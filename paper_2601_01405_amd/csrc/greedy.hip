@@ -1,0 +1,171 @@
+// greedy.hip — the blocked form of the greedy eps-net of Sec. 2.2.
+//
+// The sequential greedy visits ranks 0..n-1 and makes every still-uncovered
+// rank a landmark.  Blocked, one step takes the next B uncovered ranks after
+// the cursor (gather), decides among them with the exact predicate which ones
+// the sequential greedy would accept (resolve + accept: candidate j is a
+// landmark iff no earlier accepted candidate has j in its ball; all of them
+// are uncovered by the landmarks of earlier blocks, whose range passes are
+// complete), and then runs one range pass for the accepted ones.  Rejected
+// candidates are members of an accepted one, so that pass covers them.
+#include "dev_common.h"
+#include "kernels.h"
+
+namespace bm {
+
+constexpr int GATHER_THREADS = 1024;
+
+// One workgroup: scans the covered bitmap from the cursor, 64 ranks per thread
+// per sweep, and lists up to B uncovered ranks in increasing order.
+__global__ __launch_bounds__(GATHER_THREADS) void k_gather(const uint64_t *covered, int64_t n,
+                                                           GreedyState *st, int B, int32_t *cand)
+{
+    __shared__ int sh_scan[GATHER_THREADS / 64];
+    __shared__ int64_t sh_cursor;
+    const int64_t nwords = (n + 63) >> 6;
+    int64_t cur = st->cursor;
+    int count = 0;
+    if (threadIdx.x == 0) sh_cursor = n;
+    __syncthreads();
+    while (cur < n && count < B) {
+        const int64_t w0 = cur >> 6;
+        const int64_t w = w0 + threadIdx.x;
+        uint64_t m = 0;
+        if (w < nwords) {
+            m = ~covered[w];
+            if (w == w0) m &= (~0ull) << (cur & 63);
+            if (w == nwords - 1 && (n & 63)) m &= (1ull << (n & 63)) - 1;
+        }
+        int total;
+        int pre = block_excl_scan<GATHER_THREADS>((int)__popcll(m), &total, sh_scan);
+        const int room = B - count;
+        int k = pre;
+        while (m && k < room) {
+            int b = __ffsll((unsigned long long)m) - 1;
+            int64_t r = (w << 6) + b;
+            cand[count + k] = (int32_t)r;
+            if (count + k == B - 1) sh_cursor = r + 1;
+            m &= m - 1;
+            ++k;
+        }
+        if (total >= room) {
+            count = B;
+        } else {
+            count += total;
+            cur = (w0 + GATHER_THREADS) << 6;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st->nc = count;
+        st->na = 0;
+        st->cursor = (count == B) ? sh_cursor : n;
+    }
+}
+
+hipError_t launch_gather(const uint64_t *covered, int64_t n, GreedyState *st, int B, int32_t *cand,
+                         hipStream_t s)
+{
+    k_gather<<<1, GATHER_THREADS, 0, s>>>(covered, n, st, B, cand);
+    return hipGetLastError();
+}
+
+// Conflict words: C[j * nw + w] bit i' = 1 iff candidate i = 64 w + i' < j and
+// cand[i] has cand[j] in its ball.  One wave per (row j, word w) with 64 w < j.
+__global__ __launch_bounds__(256) void k_resolve_exact(PointsView P, double e2, const int32_t *cand,
+                                                       const GreedyState *st, int nw, uint64_t *C)
+{
+    const int nc = st->nc;
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int w = blockIdx.x;
+    if (j >= nc || (w << 6) >= j) return;      // wave-uniform
+    const int i = (w << 6) + lane_id();
+    bool hit = false;
+    if (i < j) hit = exact_member(P, orig_index(P, cand[i]), orig_index(P, cand[j]), e2);
+    uint64_t m = __ballot(hit);
+    if (lane_id() == 0) C[(int64_t)j * nw + w] = m;
+}
+
+hipError_t launch_resolve_exact(const PointsView &P, double e2, const int32_t *cand, const GreedyState *st,
+                                int B, uint64_t *C, hipStream_t s)
+{
+    const int nw = (B + 63) / 64;
+    dim3 grid(nw, (B + 3) / 4);
+    k_resolve_exact<<<grid, 256, 0, s>>>(P, e2, cand, st, nw, C);
+    return hipGetLastError();
+}
+
+// Acceptance in rank order, by rounds: a candidate is rejected as soon as one
+// of its earlier conflicts is accepted, and accepted once all of them are
+// rejected.  Decisions never change, so a stale view only delays one; the
+// earliest undecided candidate always has all its conflicts decided, so every
+// round decides at least one.  The result equals the sequential scan.
+constexpr int ACCEPT_THREADS = 1024;
+constexpr int MAX_B = 4096;
+
+__global__ __launch_bounds__(ACCEPT_THREADS) void k_accept(const uint64_t *C, int nw, const int32_t *cand,
+                                                           GreedyState *st, int32_t *A, int32_t *lm_out,
+                                                           const int32_t *perm)
+{
+    __shared__ unsigned long long acc[MAX_B / 64], rej[MAX_B / 64];
+    __shared__ int sh_undecided, sh_scan[ACCEPT_THREADS / 64];
+    const int nc = st->nc;
+    for (int t = threadIdx.x; t < MAX_B / 64; t += blockDim.x) acc[t] = rej[t] = 0ull;
+    __syncthreads();
+    unsigned long long rounds = 0;
+    for (;;) {
+        if (threadIdx.x == 0) sh_undecided = 0;
+        __syncthreads();
+        for (int j = threadIdx.x; j < nc; j += blockDim.x) {
+            const int wj = j >> 6;
+            const unsigned long long bit = 1ull << (j & 63);
+            if ((acc[wj] | rej[wj]) & bit) continue;
+            bool any_acc = false, any_open = false;
+            const int nwj = (j + 63) >> 6;       // words holding candidates < j
+            for (int w = 0; w < nwj && !any_acc; ++w) {
+                unsigned long long c = C[(int64_t)j * nw + w];
+                unsigned long long a = __atomic_load_n(&acc[w], __ATOMIC_RELAXED);
+                unsigned long long r = __atomic_load_n(&rej[w], __ATOMIC_RELAXED);
+                if (c & a) any_acc = true;
+                else if (c & ~(a | r)) any_open = true;
+            }
+            if (any_acc) atomicOr(&rej[wj], bit);
+            else if (!any_open) atomicOr(&acc[wj], bit);
+            else sh_undecided = 1;
+        }
+        __syncthreads();
+        ++rounds;
+        const int und = sh_undecided;
+        __syncthreads();
+        if (!und) break;
+    }
+    // compaction of the accepted candidates, in rank order
+    int total = 0;
+    int mine = 0;
+    const int per = (nc + ACCEPT_THREADS - 1) / ACCEPT_THREADS;   // candidates per thread, contiguous
+    const int j0 = threadIdx.x * per;
+    for (int j = j0; j < j0 + per && j < nc; ++j) mine += (int)((acc[j >> 6] >> (j & 63)) & 1ull);
+    int pos = block_excl_scan<ACCEPT_THREADS>(mine, &total, sh_scan);
+    for (int j = j0; j < j0 + per && j < nc; ++j) {
+        if ((acc[j >> 6] >> (j & 63)) & 1ull) {
+            const int32_t r = cand[j];
+            A[pos] = r;
+            lm_out[pos] = perm ? perm[r] : r;
+            ++pos;
+        }
+    }
+    if (threadIdx.x == 0) {
+        st->na = total;
+        st->rounds += rounds;
+    }
+}
+
+hipError_t launch_accept(const uint64_t *C, const int32_t *cand, GreedyState *st, int B, int32_t *A,
+                         int32_t *landmarks_out, const int32_t *perm, hipStream_t s)
+{
+    if (B > MAX_B) return hipErrorInvalidValue;
+    k_accept<<<1, ACCEPT_THREADS, 0, s>>>(C, (B + 63) / 64, cand, st, A, landmarks_out, perm);
+    return hipGetLastError();
+}
+
+} // namespace bm

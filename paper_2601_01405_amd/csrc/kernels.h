@@ -1,0 +1,68 @@
+// kernels.h — host-side launchers of the gfx950 kernels (all asynchronous on `s`).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "bm_internal.h"
+
+namespace bm {
+
+// ---- preparation (prep.hip) ------------------------------------------------------------
+// Sets *bad = 1 if any coordinate is NaN or infinite.
+hipError_t launch_check_finite(const void *X, int32_t dtype, int64_t count, int *bad, hipStream_t s);
+
+// Per point (by rank): nu[r] = |x_r|^2 in FP64; maxima of |x|^2 and of |x_k| go to
+// stats[0], stats[1] as the bit patterns of non-negative doubles.
+hipError_t launch_point_stats(const PointsView &P, double *nu, unsigned long long *stats, hipStream_t s);
+
+// FP32 copy of the points in rank order (round to nearest).
+hipError_t launch_to_f32(const PointsView &P, float *xf, hipStream_t s);
+
+// MFMA operand rows (rank order, 16-bit words, row length kpad) and per-point
+// threshold pairs, see range_mfma.hip.
+hipError_t launch_mfma_prep(const PointsView &P, int kind, int kpad, uint16_t *opnd, hipStream_t s);
+
+// ---- greedy (greedy.hip) ----------------------------------------------------------------
+hipError_t launch_gather(const uint64_t *covered, int64_t n, GreedyState *st, int B, int32_t *cand,
+                         hipStream_t s);
+hipError_t launch_resolve_exact(const PointsView &P, double e2, const int32_t *cand, const GreedyState *st,
+                                int B, uint64_t *C, hipStream_t s);
+hipError_t launch_accept(const uint64_t *C, const int32_t *cand, GreedyState *st, int B, int32_t *A,
+                         int32_t *landmarks_out, const int32_t *perm, hipStream_t s);
+
+// ---- range passes -----------------------------------------------------------------------
+// Fixed-landmark or greedy range pass: landmarks A[0..*na) (ranks), ordinals
+// ord0 + i.  Members are appended as keys (ordinal << bn | original index) and
+// their covered bits set.
+struct RangeOut {
+    uint64_t *covered;              // rank-order bitmap, may be null (fixed-landmark mode)
+    uint64_t *keys;
+    unsigned long long cap;
+    GreedyState *st;                // nkeys / band counters
+    int32_t bn;                     // bits of the original index in a key
+};
+
+hipError_t launch_range_fp32(const float *xf, const PointsView &P, double e2, Fp32Thresholds thr,
+                             int refine, const int32_t *A, const int32_t *na_dev, int na_max,
+                             int64_t ord0, const RangeOut &o, hipStream_t s);
+
+// ---- membership CSR (csr.hip) -------------------------------------------------------------
+hipError_t sort_keys(void *tmp, size_t *tmp_bytes, const uint64_t *in, uint64_t *out, size_t count,
+                     int end_bit, hipStream_t s);
+hipError_t launch_csr_from_sorted(const uint64_t *keys, int64_t M, int64_t L, int32_t bn,
+                                  int64_t *row_ptr, int32_t *member_idx, hipStream_t s);
+
+// ---- edges (edges.hip) ----------------------------------------------------------------------
+hipError_t scan_excl_i64(void *tmp, size_t *tmp_bytes, const int64_t *in, int64_t *out, size_t count,
+                         hipStream_t s);
+hipError_t launch_point_degree(const int32_t *member_idx, int64_t M, int64_t *cnt, hipStream_t s);
+// S(x): the landmarks whose ball holds x, from the sorted membership keys.
+hipError_t launch_fill_slists(const uint64_t *keys, int64_t M, int32_t bn, const int64_t *sptr,
+                              int64_t *sfill, int32_t *slist, hipStream_t s);
+// mode 0: deg[i] = number of neighbours j > i;  mode 1: write them at eptr[i].
+hipError_t launch_edge_pass(int mode, int64_t L, const int64_t *row_ptr, const int32_t *member_idx,
+                            const int64_t *sptr, const int32_t *slist, int64_t *deg,
+                            const int64_t *eptr, int32_t *edges, hipStream_t s);
+
+} // namespace bm

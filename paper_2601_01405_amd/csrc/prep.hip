@@ -1,0 +1,97 @@
+// prep.hip — one streaming pass over the stored points: finiteness check,
+// FP64 squared norms (Sec. 3.2 precomputes d^2(x,0) once per point), range
+// statistics for the error bounds, and the FP32 copy used by the plain path.
+#include "dev_common.h"
+#include "kernels.h"
+
+namespace bm {
+
+template <int DT>
+__global__ void k_check_finite(const void *X, int64_t count, int *bad)
+{
+    int found = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double v = load_coord<DT>(X, i);
+        found |= !__builtin_isfinite(v);
+    }
+    if (__ballot(found) && lane_id() == 0) atomicOr(bad, 1);
+}
+
+hipError_t launch_check_finite(const void *X, int32_t dtype, int64_t count, int *bad, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (dtype == 0) k_check_finite<0><<<(int)blocks, 256, 0, s>>>(X, count, bad);
+    else if (dtype == 1) k_check_finite<1><<<(int)blocks, 256, 0, s>>>(X, count, bad);
+    else k_check_finite<2><<<(int)blocks, 256, 0, s>>>(X, count, bad);
+    return hipGetLastError();
+}
+
+// Non-negative doubles order like their bit patterns, so a 64-bit atomicMax keeps the maximum.
+__device__ __forceinline__ void atomic_max_nonneg(unsigned long long *slot, double v)
+{
+    atomicMax(slot, (unsigned long long)__double_as_longlong(v));
+}
+
+template <int DT>
+__global__ void k_point_stats(PointsView P, double *nu, unsigned long long *stats)
+{
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double s = 0.0, mabs = 0.0;
+    if (r < P.n) {
+        const int64_t o = orig_index(P, r) * (int64_t)P.d;
+        for (int32_t k = 0; k < P.d; ++k) {
+            double v = load_coord<DT>(P.X, o + k);
+            s = __fma_rn(v, v, s);
+            mabs = fmax(mabs, fabs(v));
+        }
+        nu[r] = s;
+    }
+    // wave maxima, then one atomic per wave
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        s = fmax(s, __shfl_xor(s, off, 64));
+        mabs = fmax(mabs, __shfl_xor(mabs, off, 64));
+    }
+    if (lane_id() == 0) {
+        atomic_max_nonneg(&stats[0], s);
+        atomic_max_nonneg(&stats[1], mabs);
+    }
+}
+
+hipError_t launch_point_stats(const PointsView &P, double *nu, unsigned long long *stats, hipStream_t s)
+{
+    if (P.n <= 0) return hipSuccess;
+    int blocks = (int)((P.n + 255) / 256);
+    if (P.dtype == 0) k_point_stats<0><<<blocks, 256, 0, s>>>(P, nu, stats);
+    else if (P.dtype == 1) k_point_stats<1><<<blocks, 256, 0, s>>>(P, nu, stats);
+    else k_point_stats<2><<<blocks, 256, 0, s>>>(P, nu, stats);
+    return hipGetLastError();
+}
+
+template <int DT>
+__global__ void k_to_f32(PointsView P, float *xf)
+{
+    const int64_t total = P.n * (int64_t)P.d;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = i / P.d, k = i - r * P.d;
+        xf[i] = (float)load_coord<DT>(P.X, orig_index(P, r) * (int64_t)P.d + k);
+    }
+}
+
+hipError_t launch_to_f32(const PointsView &P, float *xf, hipStream_t s)
+{
+    const int64_t total = P.n * (int64_t)P.d;
+    if (total <= 0) return hipSuccess;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    if (P.dtype == 0) k_to_f32<0><<<(int)blocks, 256, 0, s>>>(P, xf);
+    else if (P.dtype == 1) k_to_f32<1><<<(int)blocks, 256, 0, s>>>(P, xf);
+    else k_to_f32<2><<<(int)blocks, 256, 0, s>>>(P, xf);
+    return hipGetLastError();
+}
+
+} // namespace bm

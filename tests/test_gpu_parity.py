@@ -1,0 +1,176 @@
+"""Parity of the HIP path with the FP64 oracle, element by element.
+
+Every case prints what it runs (shape, eps, path, block) before touching the
+GPU.  Sizes span several tiles with a ragged tail; the oracle finishes each
+case in seconds.
+"""
+import ctypes
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2601_01405_amd as bm
+from paper_2601_01405_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+EXACT_PATHS = ["fp32"]
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def assert_same(got, ref, what=""):
+    for name in ("landmarks", "member_ptr", "member_idx", "edges"):
+        a, b = getattr(got, name), getattr(ref, name)
+        if a.shape != b.shape or not np.array_equal(a, b):
+            if a.shape == b.shape:
+                i = int(np.argmax((a != b).reshape(-1)))
+                detail = f"first diff at flat index {i}: {a.reshape(-1)[i]} vs {b.reshape(-1)[i]}"
+            else:
+                detail = f"shapes {a.shape} vs {b.shape}"
+            raise AssertionError(f"{what}: {name} differs ({detail})")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if bm.device_count() == 0:
+        pytest.skip("no GPU visible")
+
+
+@pytest.mark.parametrize("path", EXACT_PATHS)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32, np.float16])
+def test_hand_computed_line(path, dtype):
+    g = json.load(open(os.path.join(GOLDEN, "line7_eps1.json")))
+    x = np.asarray(g["points"], dtype=dtype)[:, None]
+    for key, order in (("index_order", None), ("reverse_order", g["reverse_order"]["order"])):
+        say("line7", key, path, dtype.__name__)
+        got = bm.build(x, g["eps"], order=order, path=path)
+        exp = g[key]
+        assert got.landmarks.tolist() == exp["landmarks"]
+        assert got.member_ptr.tolist() == exp["member_ptr"]
+        assert got.member_idx.tolist() == exp["member_idx"]
+        assert got.edges.tolist() == exp["edges"]
+
+
+@pytest.mark.parametrize("path", EXACT_PATHS)
+def test_small_3d_config(path):
+    x = W.small_3d(2000)
+    say("gauss3d n=2000 eps=0.5", path)
+    assert_same(bm.build(x, 0.5, path=path), oracle.build(x, 0.5), f"gauss3d {path}")
+
+
+@pytest.mark.parametrize("path", EXACT_PATHS)
+@pytest.mark.parametrize("B", [1, 7, 64, 300, 4096])
+def test_block_sizes(path, B):
+    x = W.clusters(3001, 5, k=6, box=3.0, seed=4, dtype=np.float32)
+    say("clusters n=3001 d=5 eps=0.7", path, "B", B)
+    assert_same(bm.build(x, 0.7, path=path, block=B), oracle.build(x, 0.7), f"B={B}")
+
+
+@pytest.mark.parametrize("path", EXACT_PATHS)
+def test_clusters_16d(path):
+    x = W.clusters(6000, 16, k=10, box=20.0, seed=0, dtype=np.float32)
+    for eps in (1.0, 2.0, 5.5):
+        say("clusters16d n=6000", eps, path)
+        assert_same(bm.build(x, eps, path=path), oracle.build(x, eps), f"clusters16d eps={eps}")
+
+
+@pytest.mark.parametrize("path", EXACT_PATHS)
+def test_gaussian_128d(path):
+    x = W.gaussian(3000, 128, seed=0, dtype=np.float32)
+    for eps in (13.0, 14.5):
+        say("gauss128d n=3000", eps, path)
+        assert_same(bm.build(x, eps, path=path), oracle.build(x, eps), f"gauss128d eps={eps}")
+
+
+@pytest.mark.parametrize("path", EXACT_PATHS)
+def test_torus_64d_f16(path):
+    x = W.torus(8000, 64, seed=0, dtype=np.float16)
+    for eps in (0.1, 0.3):
+        say("torus64d n=8000 f16", eps, path)
+        assert_same(bm.build(x, eps, path=path), oracle.build(x, eps), f"torus eps={eps}")
+
+
+@pytest.mark.parametrize("path", EXACT_PATHS)
+def test_random_order(path):
+    x = W.clusters(2500, 8, k=5, box=4.0, seed=9, dtype=np.float64)
+    order = np.random.default_rng(3).permutation(2500)
+    say("clusters n=2500 d=8 random order", path)
+    assert_same(bm.build(x, 1.5, order=order, path=path, block=128), oracle.build(x, 1.5, order=order), "order")
+
+
+@pytest.mark.parametrize("path", EXACT_PATHS)
+def test_edge_cases(path):
+    say("edge cases", path)
+    empty = bm.build(np.zeros((0, 3), np.float32), 1.0, path=path)
+    assert empty.n_landmarks == 0 and empty.member_ptr.tolist() == [0] and empty.n_edges == 0
+    one = bm.build(np.ones((1, 5), np.float32), 1.0, path=path)
+    assert one.landmarks.tolist() == [0] and one.member_idx.tolist() == [0]
+    dup = np.array([[1.0, 2.0], [1.0, 2.0], [5.0, 5.0], [1.0, 2.0]])
+    assert_same(bm.build(dup, 0.1, path=path), oracle.build(dup, 0.1), "duplicates")
+    x = W.gaussian(777, 4, seed=5)
+    assert_same(bm.build(x, 100.0, path=path), oracle.build(x, 100.0), "eps above diameter")
+    assert_same(bm.build(x, 1e-3, path=path), oracle.build(x, 1e-3), "tiny eps")
+    grid = np.random.default_rng(3).integers(-4, 5, (513, 3)).astype(np.float32) / 2
+    for eps in (0.5, 1.0, 1.5):       # exact ties at eps on a dyadic grid
+        assert_same(bm.build(grid, eps, path=path), oracle.build(grid, eps), f"grid ties eps={eps}")
+
+
+@pytest.mark.parametrize("path", EXACT_PATHS)
+def test_member_buffer_regrowth(path):
+    x = W.gaussian(2000, 6, seed=1, dtype=np.float32)
+    say("regrow n=2000", path)
+    assert_same(bm.build(x, 2.5, path=path, init_member_capacity=1, block=64), oracle.build(x, 2.5), "regrow")
+
+
+def test_results_on_device_and_torch_input():
+    import torch
+    x = W.clusters(4000, 16, k=10, seed=2, dtype=np.float32)
+    ref = oracle.build(x, 2.0)
+    say("torch device input, results on device")
+    xd = torch.from_numpy(x).cuda()
+    got = bm.build(xd, 2.0, path="fp32")
+    assert_same(got, ref, "torch input")
+    hip = ctypes.CDLL("libamdhip64.so")
+    with bm.build(xd, 2.0, path="fp32", results_on_device=True) as r:
+        assert (r.n_landmarks, r.n_edges) == (ref.n_landmarks, ref.n_edges)
+        idx = np.empty(int(ref.member_ptr[-1]), np.int32)
+        assert hip.hipMemcpy(ctypes.c_void_p(idx.ctypes.data), ctypes.c_void_p(r.member_idx),
+                             ctypes.c_size_t(idx.nbytes), 2) == 0
+        assert np.array_equal(idx, ref.member_idx)
+
+
+@pytest.mark.parametrize("path", EXACT_PATHS)
+def test_fixed_landmarks(path):
+    x = W.clusters(3000, 12, k=4, box=5.0, seed=6, dtype=np.float32)
+    lm = np.random.default_rng(0).choice(3000, 200, replace=False).astype(np.int32)
+    say("fixed landmarks n=3000 L=200", path)
+    assert_same(bm.range_sets(x, lm, 3.0, path=path), oracle.range_sets(x, lm, 3.0), "fixed")
+
+
+def test_build_many_matches_single():
+    probs = W.batched(count=6, n_lo=300, n_hi=3000, seed=1)
+    say("build_many 6 problems x 8 eps")
+    many = bm.build_many([(p.points, p.eps) for p in probs], path="fp32")
+    for p, row in zip(probs, many):
+        for eps, got in zip(p.eps, row):
+            assert_same(got, oracle.build(p.points, eps), f"many n={p.points.shape} eps={eps}")
+
+
+def test_paper_gaussian_worked_example():
+    """Sec. 6.3: 6361 landmarks and 936690 edges at the target-occupancy eps."""
+    x = W.paper_gaussian()
+    eps, _ = oracle.knn_eps(x, 50)
+    say("paper gaussian n=20000 d=50 eps", eps)
+    ref = oracle.build(x, eps)
+    for path in EXACT_PATHS:
+        got = bm.build(x, eps, path=path)
+        assert got.n_landmarks == 6361 and got.n_edges == 936690
+        assert_same(got, ref, f"paper gaussian {path}")
