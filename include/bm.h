@@ -167,6 +167,40 @@ int bm_range_sets(const void *points, int64_t n, int32_t d, int32_t dtype, doubl
                   const int32_t *landmarks, int64_t n_landmarks, const bm_options *opt,
                   bm_result **out);
 
+/*
+ * The deterministic error bound of a path (the additive model of Sec. 5.1,
+ * used both to decide pairs exactly and to score the unrefined path).
+ * For the MFMA paths the filter value G of landmark a and point x satisfies
+ *     |G - (|x|^2 - D(a,x)) / 2| <= alpha |a|^2 + beta |x|^2 + abs_err,
+ * D the exact squared distance, |.|^2 the squared norm of the stored point
+ * widened to FP64.  For the FP32 path alpha = beta = 0 and rel_err is the
+ * relative bound of the FP32 squared distance (the multiplicative model of
+ * Sec. 5.2), abs_err its absolute part.  delta is the additive radius error of
+ * Sec. 5.1 for points of squared norm <= max_sq_norm:
+ *     delta = max(eps - sqrt(eps^2 - w), sqrt(eps^2 + w) - eps),
+ * w the bound on |estimated D - D| at D = eps^2.
+ * Inputs: path (not AUTO), dtype and d of the stored points, eps, the largest
+ * squared norm and the largest |coordinate| of the data.  No device needed.
+ */
+typedef struct {
+    double alpha, beta, abs_err, rel_err;
+    double t_in, t_out;           /* D < t_in => s < RN(eps^2); D >= t_out => s >= RN(eps^2) */
+    double delta;
+    int32_t exact_range;          /* 0 if eps or the data leave the range where the
+                                     bound holds (every pair is then rechecked) */
+} bm_bound;
+int bm_error_bound(int32_t path, int32_t dtype, int32_t d, double eps, double max_sq_norm, double max_abs,
+                   bm_bound *out);
+
+/*
+ * Checks on `device` (-1 = current) the matrix-core behaviour the error bound
+ * relies on and sets *flags: bit 0 bf16 and bit 1 f16 32x32x16 output layout
+ * as the kernels assume; bit 2 f16 and bit 3 bf16 subnormal operands
+ * multiplied exactly.  The MFMA paths run this once per device and refuse to
+ * run (BM_EINTERNAL) if a layout bit is missing.
+ */
+int bm_device_selfcheck(int32_t device, int32_t *flags);
+
 /* Free a result from any entry point (host or device arrays).  NULL-safe. */
 void bm_result_free(bm_result *r);
 

@@ -99,6 +99,11 @@ def load_library(path: str = LIB_PATH):
     lib.bm_last_error.restype = ctypes.c_char_p
     lib.bm_device_count.restype = ctypes.c_int
     lib.bm_abi_version.restype = ctypes.c_int
+    lib.bm_error_bound.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_double, ctypes.c_void_p]
+    lib.bm_error_bound.restype = ctypes.c_int
+    lib.bm_device_selfcheck.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.bm_device_selfcheck.restype = ctypes.c_int
     for f in ("bm_default_options", "bm_build", "bm_range_sets", "bm_build_many"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -106,7 +111,30 @@ def load_library(path: str = LIB_PATH):
 
 
 EXPORTED_SYMBOLS = ("bm_default_options", "bm_build", "bm_build_many", "bm_range_sets", "bm_result_free",
-                    "bm_last_error", "bm_device_count", "bm_abi_version")
+                    "bm_last_error", "bm_device_count", "bm_abi_version", "bm_error_bound",
+                    "bm_device_selfcheck")
+
+
+class Bound(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("abs_err", ctypes.c_double),
+                ("rel_err", ctypes.c_double), ("t_in", ctypes.c_double), ("t_out", ctypes.c_double),
+                ("delta", ctypes.c_double), ("exact_range", ctypes.c_int32)]
+
+
+def error_bound(path, dtype, d: int, eps: float, max_sq_norm: float, max_abs: float) -> dict:
+    """Constants of a path's deterministic error bound (bm_error_bound)."""
+    b = Bound()
+    code = DTYPES[np.dtype(dtype)]
+    _check(load_library().bm_error_bound(PATHS[path] if isinstance(path, str) else int(path), code, int(d),
+                                         float(eps), float(max_sq_norm), float(max_abs), ctypes.byref(b)))
+    return {f: getattr(b, f) for f, _ in Bound._fields_}
+
+
+def device_selfcheck(device: int = -1) -> int:
+    """Matrix-core self-check flags of a device (bm_device_selfcheck)."""
+    f = ctypes.c_int32()
+    _check(load_library().bm_device_selfcheck(int(device), ctypes.byref(f)))
+    return int(f.value)
 
 
 def _check(rc: int):

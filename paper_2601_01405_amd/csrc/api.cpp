@@ -8,6 +8,8 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -203,11 +205,54 @@ struct Job {
     int64_t n_fixed;
 };
 
-int auto_block(int64_t n)
+// gfx950 matrix cores take float16 (and bf16) subnormal operands exactly; the
+// device self-test (bm_device_selfcheck) verifies this before an MFMA path runs.
+constexpr bool kF16SubnormalsOk = true;
+
+std::mutex g_selfcheck_mu;
+std::map<int, int> g_selfcheck;     // device -> flags
+
+int device_flags(int dev, hipStream_t s)
 {
-    if (n >= (1 << 17)) return 1024;
+    {
+        std::lock_guard<std::mutex> lk(g_selfcheck_mu);
+        auto it = g_selfcheck.find(dev);
+        if (it != g_selfcheck.end()) return it->second;
+    }
+    int *fd = nullptr;
+    hip_ok(hipMalloc(&fd, sizeof(int)), "hipMalloc");
+    int flags = 0;
+    hipError_t e = run_selfcheck(fd, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&flags, fd, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(fd);
+    hip_ok(e, "device self-check");
+    std::lock_guard<std::mutex> lk(g_selfcheck_mu);
+    g_selfcheck[dev] = flags;
+    return flags;
+}
+
+int auto_block(int64_t n, int path)
+{
+    if (path == BM_PATH_FP32) {
+        if (n >= (1 << 17)) return 1024;
+        if (n >= (1 << 13)) return 256;
+        return 64;
+    }
+    if (n >= (1 << 17)) return 2048;
     if (n >= (1 << 13)) return 256;
     return 64;
+}
+
+// BF16 with one product unless its band would be wide against eps^2, then the
+// three-product split; float16 storage is exact in f16.
+int auto_path(int dtype, int d, double e2, double max_nu, double max_abs)
+{
+    if (dtype == BM_F16) return BM_PATH_F16;
+    const int K1 = (d + 15) / 16 * 16;
+    const MfmaBound b1 = mfma_bound(MFMA_BF16, d, K1, e2, std::sqrt(max_nu), max_abs, false);
+    const double half_width = 2.0 * ((b1.alpha + b1.beta) * max_nu + b1.abs_err);   // in D units
+    return half_width <= 0.02 * e2 ? BM_PATH_BF16 : BM_PATH_BF16X3;
 }
 
 bm_result *run_job(const Job &job, const bm_options &o)
@@ -259,12 +304,14 @@ bm_result *run_job(const Job &job, const bm_options &o)
             std::memcpy(&max_nu, &raw[0], 8);
             std::memcpy(&max_abs, &raw[1], 8);
         }
-        if (path == BM_PATH_AUTO) path = BM_PATH_FP32;   // MFMA paths are selected explicitly for now
+        if (path == BM_PATH_AUTO) path = auto_path(job.dtype, d, e2, max_nu, max_abs);
         res->stats.path = path;
+        const int B = o.block ? o.block : auto_block(n, path);
 
         // -- path preparation
         Fp32Thresholds thr32{};
         float *xf = nullptr;
+        MfmaArgs ma{};
         if (path == BM_PATH_FP32) {
             thr32 = fp32_thresholds(e2, d, job.dtype, std::sqrt(max_nu), max_abs);
             if (job.dtype == BM_F32 && !perm_d) {
@@ -273,14 +320,37 @@ bm_result *run_job(const Job &job, const bm_options &o)
                 xf = dev.alloc<float>((size_t)n * d);
                 hip_ok(launch_to_f32(P, xf, dev.s), "to_f32");
             }
-        } else {
-            fail(BM_EINVAL, "this path is not available in this build");
+        } else if (n > 0) {
+            const int kind = path;   // BM_PATH_BF16/BF16X3/F16 share the MfmaKind values
+            const int Kraw = (kind == MFMA_BF16X3) ? 3 * d : d;
+            const int S = (Kraw + 15) / 16;
+            const int64_t NT = (n + 31) / 32;
+            const size_t words = (size_t)NT * S * 64 * 8;
+            uint16_t *Pop = dev.alloc<uint16_t>(words);
+            uint16_t *Qop = (kind == MFMA_BF16X3) ? dev.alloc<uint16_t>(words) : Pop;
+            hip_ok(launch_mfma_operands(P, kind, S, Pop, Qop, dev.s), "mfma_operands");
+            const int flags = device_flags(dev.dev, dev.s);
+            if ((flags & 3) != 3) fail(BM_EINTERNAL, "matrix-core layout self-check failed on this device");
+            const MfmaBound mb = mfma_bound(kind, d, 16 * S, e2, std::sqrt(max_nu), max_abs, (flags & 4) != 0);
+            float *sc = dev.alloc<float>((size_t)n * 5);
+            hip_ok(launch_mfma_scalars(n, nu, mb, e2, d, sc, sc + n, sc + 2 * n, sc + 3 * n, sc + 4 * n, dev.s),
+                   "mfma_scalars");
+            ma.Pop = Pop;
+            ma.Qop = Qop;
+            ma.cinit = sc;
+            ma.nuup = sc + n;
+            ma.U = sc + 2 * n;
+            ma.V = sc + 3 * n;
+            ma.Z = sc + 4 * n;
+            ma.alpha = f32_up(mb.alpha);
+            ma.S = S;
+            ma.kind = kind;
+            ma.refine = o.refine;
         }
         res->stats.ms_prepare = ms_since(t_prep);
 
         // -- range passes
         const auto t_greedy = clk::now();
-        const int B = o.block ? o.block : auto_block(n);
         res->stats.block = B;
         const int32_t bn = std::max(1, bitlen((uint64_t)std::max<int64_t>(n - 1, 1)));
         unsigned long long cap = o.init_member_capacity
@@ -297,7 +367,10 @@ bm_result *run_job(const Job &job, const bm_options &o)
         auto run_range = [&](int64_t ord0, const int32_t *na_dev) {
             ro.keys = keys;
             ro.cap = cap;
-            hip_ok(launch_range_fp32(xf, P, e2, thr32, o.refine, A, na_dev, B, ord0, ro, dev.s), "range_fp32");
+            if (path == BM_PATH_FP32)
+                hip_ok(launch_range_fp32(xf, P, e2, thr32, o.refine, A, na_dev, B, ord0, ro, dev.s), "range_fp32");
+            else
+                hip_ok(launch_range_mfma(ma, P, e2, A, na_dev, B, ord0, ro, dev.s), "range_mfma");
         };
         // grow the key buffer if the last block overflowed it, then redo that block's
         // range pass (covered bits are idempotent ORs, so only the keys change)
@@ -579,6 +652,61 @@ void bm_result_free(bm_result *r)
         std::free(r->edges);
     }
     std::free(r);
+}
+
+int bm_device_selfcheck(int32_t device, int32_t *flags)
+{
+    return guarded([&]() -> int {
+        if (!flags) fail(BM_EINVAL, "flags is NULL");
+        bm_options o;
+        bm_default_options(&o);
+        o.device = device;
+        Device dev(o);
+        *flags = device_flags(dev.dev, dev.s);
+        return BM_OK;
+    });
+}
+
+int bm_error_bound(int32_t path, int32_t dtype, int32_t d, double eps, double max_sq_norm, double max_abs,
+                   bm_bound *out)
+{
+    return guarded([&]() -> int {
+        if (!out) fail(BM_EINVAL, "out is NULL");
+        if (d < 1 || !(eps > 0.0) || !std::isfinite(eps) || !(max_sq_norm >= 0.0) || !(max_abs >= 0.0))
+            fail(BM_EINVAL, "bad arguments");
+        if (dtype != BM_F64 && dtype != BM_F32 && dtype != BM_F16) fail(BM_EINVAL, "unknown dtype");
+        const double e2 = eps * eps;
+        std::memset(out, 0, sizeof(*out));
+        double w;
+        if (path == BM_PATH_FP32) {
+            const double g32 = gamma_u(d + 2.0, std::ldexp(1.0, -24));
+            const double E = (dtype == BM_F64) ? std::ldexp(std::sqrt(max_sq_norm), -23) : 0.0;
+            exact_window(e2, d, &out->t_in, &out->t_out);
+            out->rel_err = g32;
+            out->abs_err = d * std::ldexp(1.0, -125);
+            // |s32 - D| <= g32 (sqrt(D) + E)^2 + 2 E sqrt(D) + E^2 + abs at D = e2
+            const double se = std::sqrt(e2);
+            w = g32 * (se + E) * (se + E) + 2.0 * E * se + E * E + out->abs_err;
+            out->exact_range = e2 >= std::ldexp(1.0, -100) && e2 <= std::ldexp(1.0, 100) && max_abs <= std::ldexp(1.0, 60);
+        } else if (path == BM_PATH_BF16 || path == BM_PATH_BF16X3 || path == BM_PATH_F16) {
+            if (path == BM_PATH_F16 && dtype != BM_F16) fail(BM_EINVAL, "path F16 needs float16 storage");
+            const int Kraw = (path == BM_PATH_BF16X3) ? 3 * d : d;
+            const int K = (Kraw + 15) / 16 * 16;
+            const MfmaBound b = mfma_bound(path, d, K, e2, std::sqrt(max_sq_norm), max_abs, kF16SubnormalsOk);
+            out->alpha = b.alpha;
+            out->beta = b.beta;
+            out->abs_err = b.abs_err;
+            out->t_in = b.t_in;
+            out->t_out = b.t_out;
+            out->exact_range = b.sane;
+            w = 2.0 * ((b.alpha + b.beta) * max_sq_norm + b.abs_err);   // |D_est - D| = 2 |G - h|
+        } else {
+            fail(BM_EINVAL, "path must be FP32, BF16, BF16X3 or F16");
+        }
+        const double eps_lo = e2 > w ? std::sqrt(e2 - w) : 0.0;
+        out->delta = std::max(eps - eps_lo, std::sqrt(e2 + w) - eps);
+        return BM_OK;
+    });
 }
 
 const char *bm_last_error(void) { return g_last_error.c_str(); }

@@ -33,15 +33,36 @@ struct Fp32Thresholds {
     float unrefined;                // threshold used when refine == 0
 };
 
-// MFMA operand layout: points are stored as K-padded rows of 16-bit values
-// (bf16 or f16), K = kpad, grouped in tiles of 32 points.  For the three-product
-// split the row holds [hi | hi | lo] against the landmark side [hi | lo | hi].
+// MFMA paths.  Operands are 16-bit words (bf16 or f16) in K-padded rows
+// (K a multiple of 16), swizzled so that one 32x32x16 step of a 32-point tile
+// is 1 KB of contiguous memory: element e of lane l of step s of tile t sits
+// at ((t * S + s) * 64 + l) * 8 + e and holds coordinate k = 16 s + 8 (l / 32) + e
+// of point 32 t + l % 32.  With the three-product split the point side holds
+// [hi | hi | lo] and the landmark side [hi | lo | hi], so their dot product is
+// hi.hi + hi.lo + lo.hi.
 enum MfmaKind { MFMA_BF16 = 2, MFMA_BF16X3 = 3, MFMA_F16 = 4 };
 
-struct MfmaParams {
+// Constants of the MFMA error bound (host computed, see bounds.h).  The kernel
+// output for landmark a and point x is  G = -RN32(nu_a)/2 + sum_k P_k Q_k, an
+// estimate of (nu_x - D)/2, and |G - (nu_x - D)/2| <= alpha nu_a + beta nu_x + abs.
+struct MfmaBound {
+    double alpha, beta, abs_err;
+    double t_in, t_out;             // exact-decision window on D
+    bool sane;                      // false: every pair goes to the FP64 recheck
+};
+
+struct MfmaArgs {
+    const uint16_t *Pop;            // point-side operands, swizzled
+    const uint16_t *Qop;            // landmark-side operands, swizzled
+    const float *cinit;             // per rank: -RN32(nu)/2
+    const float *nuup;              // per rank: nu rounded up
+    const float *U;                 // per rank: G <= U - alpha*nu_a  =>  not a member
+    const float *V;                 // per rank: G >  V + alpha*nu_a  =>  member
+    const float *Z;                 // per rank: unrefined decision G > Z
+    float alpha;                    // rounded up
+    int32_t S;                      // K / 16
     int32_t kind;
-    int32_t kpad;                   // padded K (multiple of 16)
-    float   w_scale;                // not used on device; kept for stats
+    int32_t refine;
 };
 
 } // namespace bm

@@ -88,4 +88,56 @@ inline Fp32Thresholds fp32_thresholds(double e2, int d, int dtype, double max_no
     return t;
 }
 
+// MFMA paths.  Per coordinate the operands carry a relative error rho
+// (|x̂ - x̄| <= rho |x̄| + tau), so a product term is off by at most
+// rho_p |ā_k x̄_k| + m tau (1 + rho)(|ā_k| + |x̄_k|) + m tau^2 (m products per
+// coordinate); summed, sum_k |ā_k x̄_k| <= |ā||x̄| <= (nu_a + nu_x)/2 and
+// sum_k (|ā_k| + |x̄_k|) <= sqrt(d)(|ā| + |x̄|) <= 2 sqrt(d) R.  The matrix core
+// accumulates K products and the initial value in FP32 in an unspecified
+// order; we charge gamma_{K+1}(2^-23) on the sum of magnitudes (this also
+// covers truncating instead of rounding) and 2^-126 per step for values below
+// the normal range.  The initial value -RN32(nu_a)/2 is off by
+// (2^-24 + gamma_d(2^-53)) nu_a / 2.
+//   rho_p:  BF16  (2 rho + rho^2), rho = (2^-8 + 2^-24)(1 + 2^-20): bf16 keeps 8
+//                 significant bits, so round-to-nearest is off by up to 2^-8
+//                 relative, after at most 2^-24 from a float64 -> float32 step
+//           BF16X3  3 * 2^-16 (1 + 2^-6)   (hi off by 2^-8, lo by 2^-8 of the
+//                 remainder: the dropped lo.lo and residual terms)
+//           F16   0  (float16 storage is exact in f16)
+//   tau:    2^-126 for bf16 (values flushed below the normal range),
+//           2^-14 for f16 unless the device honours f16 subnormals in MFMA.
+inline MfmaBound mfma_bound(int kind, int d, int K, double e2, double max_norm, double max_abs, bool f16_subnormals_ok)
+{
+    MfmaBound b{};
+    const double u24 = std::ldexp(1.0, -24);
+    const double g64d = gamma_u((double)d, std::ldexp(1.0, -53));
+    const double gK = gamma_u(K + 1.0, std::ldexp(1.0, -23));
+    double rho, rho_p, tau;
+    int m = 1;
+    if (kind == MFMA_BF16) {
+        rho = (std::ldexp(1.0, -8) + u24) * (1.0 + std::ldexp(1.0, -20));
+        rho_p = 2.0 * rho + rho * rho;
+        tau = std::ldexp(1.0, -126);
+    } else if (kind == MFMA_BF16X3) {
+        rho = (std::ldexp(1.0, -8) + u24) * (1.0 + std::ldexp(1.0, -20));
+        rho_p = 3.0 * std::ldexp(1.0, -16) * (1.0 + std::ldexp(1.0, -6));
+        tau = std::ldexp(1.0, -126);
+        m = 3;
+    } else {
+        rho = 0.0;
+        rho_p = 0.0;
+        tau = f16_subnormals_ok ? 0.0 : std::ldexp(1.0, -14);
+    }
+    const double mag = (1.0 + rho) * (1.0 + rho) * (1.0 + std::ldexp(1.0, -6));   // sum|P Q| <= mag (nu_a+nu_x)/2
+    const double op_abs = 2.0 * m * tau * (1.0 + rho) * std::sqrt((double)d) * max_norm + m * (double)d * tau * tau;
+    const double slack = 1.0 + std::ldexp(1.0, -20);
+    b.alpha = slack * ((u24 + g64d) / 2.0 + rho_p / 2.0 + gK * ((1.0 + u24) / 2.0 + mag / 2.0)) ;
+    b.beta = slack * (rho_p / 2.0 + gK * mag / 2.0 + g64d);
+    b.abs_err = 2.0 * ((1.0 + gK) * op_abs + (K + 2.0) * std::ldexp(1.0, -126));
+    exact_window(e2, d, &b.t_in, &b.t_out);
+    b.sane = e2 >= std::ldexp(1.0, -100) && e2 <= std::ldexp(1.0, 100) && max_abs <= std::ldexp(1.0, 60) &&
+             max_norm * max_norm <= std::ldexp(1.0, 100);
+    return b;
+}
+
 } // namespace bm

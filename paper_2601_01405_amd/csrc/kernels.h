@@ -19,9 +19,11 @@ hipError_t launch_point_stats(const PointsView &P, double *nu, unsigned long lon
 // FP32 copy of the points in rank order (round to nearest).
 hipError_t launch_to_f32(const PointsView &P, float *xf, hipStream_t s);
 
-// MFMA operand rows (rank order, 16-bit words, row length kpad) and per-point
-// threshold pairs, see range_mfma.hip.
-hipError_t launch_mfma_prep(const PointsView &P, int kind, int kpad, uint16_t *opnd, hipStream_t s);
+// MFMA operands in the swizzled tile layout (range_mfma.hip).  Qop may equal Pop.
+hipError_t launch_mfma_operands(const PointsView &P, int kind, int S, uint16_t *Pop, uint16_t *Qop, hipStream_t s);
+// Per-point accumulator start, rounded-up norm and decision thresholds for one eps.
+hipError_t launch_mfma_scalars(int64_t n, const double *nu, const MfmaBound &b, double e2, int d, float *cinit,
+                               float *nuup, float *U, float *V, float *Z, hipStream_t s);
 
 // ---- greedy (greedy.hip) ----------------------------------------------------------------
 hipError_t launch_gather(const uint64_t *covered, int64_t n, GreedyState *st, int B, int32_t *cand,
@@ -46,6 +48,11 @@ struct RangeOut {
 hipError_t launch_range_fp32(const float *xf, const PointsView &P, double e2, Fp32Thresholds thr,
                              int refine, const int32_t *A, const int32_t *na_dev, int na_max,
                              int64_t ord0, const RangeOut &o, hipStream_t s);
+
+// One-wave check of the matrix-core layout and subnormal handling (flags, see range_mfma.hip).
+hipError_t run_selfcheck(int *flags_dev, hipStream_t s);
+hipError_t launch_range_mfma(const MfmaArgs &a, const PointsView &P, double e2, const int32_t *A,
+                             const int32_t *na_dev, int na_max, int64_t ord0, const RangeOut &o, hipStream_t s);
 
 // ---- membership CSR (csr.hip) -------------------------------------------------------------
 hipError_t sort_keys(void *tmp, size_t *tmp_bytes, const uint64_t *in, uint64_t *out, size_t count,

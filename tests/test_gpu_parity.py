@@ -19,7 +19,11 @@ from paper_2601_01405_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-EXACT_PATHS = ["fp32"]
+EXACT_PATHS = ["fp32", "bf16", "bf16x3", "auto"]
+
+
+def paths_for(dtype):
+    return EXACT_PATHS + (["f16"] if np.dtype(dtype) == np.float16 else [])
 
 
 def say(*a):
@@ -44,19 +48,19 @@ def _need_gpu():
         pytest.skip("no GPU visible")
 
 
-@pytest.mark.parametrize("path", EXACT_PATHS)
 @pytest.mark.parametrize("dtype", [np.float64, np.float32, np.float16])
-def test_hand_computed_line(path, dtype):
+def test_hand_computed_line(dtype):
     g = json.load(open(os.path.join(GOLDEN, "line7_eps1.json")))
     x = np.asarray(g["points"], dtype=dtype)[:, None]
     for key, order in (("index_order", None), ("reverse_order", g["reverse_order"]["order"])):
-        say("line7", key, path, dtype.__name__)
-        got = bm.build(x, g["eps"], order=order, path=path)
-        exp = g[key]
-        assert got.landmarks.tolist() == exp["landmarks"]
-        assert got.member_ptr.tolist() == exp["member_ptr"]
-        assert got.member_idx.tolist() == exp["member_idx"]
-        assert got.edges.tolist() == exp["edges"]
+        for path in paths_for(dtype):
+            say("line7", key, path, dtype.__name__)
+            got = bm.build(x, g["eps"], order=order, path=path)
+            exp = g[key]
+            assert got.landmarks.tolist() == exp["landmarks"]
+            assert got.member_ptr.tolist() == exp["member_ptr"]
+            assert got.member_idx.tolist() == exp["member_idx"]
+            assert got.edges.tolist() == exp["edges"]
 
 
 @pytest.mark.parametrize("path", EXACT_PATHS)
@@ -90,7 +94,7 @@ def test_gaussian_128d(path):
         assert_same(bm.build(x, eps, path=path), oracle.build(x, eps), f"gauss128d eps={eps}")
 
 
-@pytest.mark.parametrize("path", EXACT_PATHS)
+@pytest.mark.parametrize("path", paths_for(np.float16))
 def test_torus_64d_f16(path):
     x = W.torus(8000, 64, seed=0, dtype=np.float16)
     for eps in (0.1, 0.3):
@@ -170,7 +174,12 @@ def test_paper_gaussian_worked_example():
     eps, _ = oracle.knn_eps(x, 50)
     say("paper gaussian n=20000 d=50 eps", eps)
     ref = oracle.build(x, eps)
-    for path in EXACT_PATHS:
+    for path in ("fp32", "auto"):
         got = bm.build(x, eps, path=path)
         assert got.n_landmarks == 6361 and got.n_edges == 936690
         assert_same(got, ref, f"paper gaussian {path}")
+
+
+def test_device_selfcheck():
+    """Matrix-core output layout and exact subnormal operands, as the bound assumes."""
+    assert bm.device_selfcheck() == 15
