@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Ball Mapper construction benchmark on one MI355X.
+
+One step = the whole hot path (greedy landmark selection by blocked range
+queries, membership CSR, nerve edges) at every eps of the workload, with the
+points already resident in HBM and the results left in device memory.  The
+headline value is landmark-point pair distances per second of the refined
+low-precision path (bit-identical to the FP64 oracle); the plain FP32 path is
+timed on the same inputs for comparison.  Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "G pair-dists/s + Ball Mapper graph time, refined-BF16 vs FP32, bit-exact"
+PEAK_BF16_TFLOPS = 2500.0       # MI355X dense bf16 matrix peak
+PEAK_F16_TFLOPS = 2500.0
+PEAK_FP32_VALU_TFLOPS = 157.3
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "range_mfma_clusters16d_n200k_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2601_01405_amd", "csrc", "range_mfma.hip")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="clusters16d_n200k_f32")
+    ap.add_argument("--path", default="auto", help="refined path (auto, bf16, bf16x3, f16)")
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    return ap.parse_args()
+
+
+def digest(r):
+    h = hashlib.sha256()
+    for a in (r.landmarks, r.member_ptr, r.member_idx, r.edges):
+        h.update(a.tobytes())
+    return h.hexdigest()
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic(pairs_per_launch_known):
+    """HBM bytes per range-pass launch from the committed rocprofv3 counter
+    summary, or None if it is missing or was taken on another kernel version."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2601_01405_amd as bm
+    from paper_2601_01405_amd import workloads as W
+
+    spec = W.WORKLOADS[args.workload]
+    x = spec["make"]()
+    eps_list = spec["eps"]
+    n, d = x.shape
+    log(f"workload {args.workload}: n={n} d={d} dtype={x.dtype} eps={eps_list}")
+    xd = torch.from_numpy(x).to("cuda:0")
+    torch.cuda.synchronize()
+
+    def step(path, profile=False):
+        out = []
+        for eps in eps_list:
+            r = bm.build(xd, eps, path=path, block=args.block, results_on_device=True, profile=profile)
+            out.append((r.stats, r.n_landmarks, r.n_edges))
+            r.free()
+        return out
+
+    # -- bit-exactness across paths, outside the timed region
+    ref_path = "fp32"
+    exact = True
+    host = {}
+    for eps in eps_list:
+        a = bm.build(xd, eps, path=args.path, block=args.block)
+        b = bm.build(xd, eps, path=ref_path, block=args.block)
+        host[eps] = a
+        same = digest(a) == digest(b)
+        exact &= same
+        log(f"eps={eps}: L={a.n_landmarks} M={int(a.member_ptr[-1])} E={a.n_edges} path={a.stats['path']} "
+            f"identical to {ref_path}: {same}")
+    # sampled check of full-size rows against the FP64 oracle (one by one)
+    import oracle
+    rng = np.random.default_rng(0)
+    for eps in eps_list:
+        a = host[eps]
+        pick = rng.choice(a.n_landmarks, min(8, a.n_landmarks), replace=False)
+        ref = oracle.range_sets(x, a.landmarks[pick], eps)
+        for j, i in enumerate(pick):
+            exact &= bool(np.array_equal(a.row(int(i)), ref.row(j)))
+    log(f"bit-exact (paths identical, sampled rows equal the oracle): {exact}")
+
+    # -- refined path, timed
+    for _ in range(args.warmup):
+        step(args.path)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [step(args.path, profile=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    pairs = sum(s["pairs_useful"] for run in runs for s, _, _ in run)
+    value = pairs / elapsed / 1e9
+    used_path = runs[0][0][0]["path"]
+    block = runs[0][0][0]["block"]
+    graph_ms = {f"eps={eps}": float(np.median([run[i][0]["ms_total"] for run in runs]))
+                for i, eps in enumerate(eps_list)}
+    range_ms = sum(s["ms_range_kernel"] for run in runs for s, _, _ in run)
+    launches = sum(s["range_launches"] for run in runs for s, _, _ in run)
+    range_pairs = sum(s["range_pairs"] for run in runs for s, _, _ in run)
+    log(f"refined {used_path}: {value:.1f} G pair-dists/s, {elapsed / args.steps * 1e3:.2f} ms/step, "
+        f"range kernels {range_ms / args.steps:.2f} ms/step over {launches // args.steps} launches")
+
+    # -- plain FP32 path on the same inputs
+    fp32 = None
+    if not args.no_fp32:
+        step("fp32")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fsteps = max(1, min(args.steps, 3))
+        fr = [step("fp32") for _ in range(fsteps)]
+        torch.cuda.synchronize()
+        fel = time.perf_counter() - t0
+        fpairs = sum(s["pairs_useful"] for run in fr for s, _, _ in run)
+        fp32 = {"value": fpairs / fel / 1e9, "ms_per_step": fel / fsteps * 1e3, "steps": fsteps}
+        log(f"fp32: {fp32['value']:.1f} G pair-dists/s, {fp32['ms_per_step']:.2f} ms/step")
+
+    # -- roofline of the range pass (dominant kernel): algorithmic flops 2d per pair
+    flops = 2.0 * d * range_pairs
+    achieved = flops / (range_ms * 1e-3) / 1e12 if range_ms > 0 else None
+    peak = PEAK_F16_TFLOPS if used_path == "f16" else PEAK_BF16_TFLOPS
+    roofline = {"bound": "mfma", "kernel": "k_range_mfma", "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s", "frac": (achieved / peak) if achieved else None,
+                "traffic": read_traffic(range_pairs / max(launches, 1)),
+                "per_launch_ms": range_ms / max(launches, 1), "launches_per_step": launches / args.steps,
+                "flops_per_pair": 2 * d}
+
+    # -- the FP64 oracle on the host, a bounded sample of the same workload
+    cpu = None
+    if not args.no_cpu_baseline:
+        eps = eps_list[0]
+        t0 = time.perf_counter()
+        probe = oracle.build(x, eps, max_landmarks=50)
+        tp = time.perf_counter() - t0
+        k = int(max(50, min(50 * args.cpu_seconds / max(tp, 1e-3), 200000)))
+        t0 = time.perf_counter()
+        smp = oracle.build(x, eps, max_landmarks=k)
+        tc = time.perf_counter() - t0
+        cpu = {"value": smp.n_landmarks * n / tc / 1e9, "unit": "G pair-dists/s", "cores": oracle.threads(),
+               "kind": "oracle",
+               "sample": f"first {smp.n_landmarks} landmarks of the greedy at eps={eps} "
+                         f"(each against all {n} points), {tc:.1f} s, incl. their CSR rows and edges"}
+        log(f"cpu oracle: {cpu['value']:.3f} G pair-dists/s on {cpu['cores']} threads ({cpu['sample']})")
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "G pair-dists/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16" if used_path != "f16" else "f16",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "d": d, "storage": str(x.dtype), "eps": eps_list,
+                   "path": used_path, "block": block, "order": "index"},
+        "graph_ms": graph_ms,
+        "landmarks": [s[1] for s in runs[0]], "edges": [s[2] for s in runs[0]],
+        "fp32_path": fp32,
+        "speedup_vs_fp32": (value / fp32["value"]) if fp32 else None,
+        "bit_exact": exact,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

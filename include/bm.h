@@ -88,6 +88,8 @@ typedef struct {
     int64_t max_device_bytes;     /* 0 = unlimited; else BM_ENOMEM beyond this many bytes      */
     int64_t init_member_capacity; /* 0 = automatic; a small value exercises buffer regrowth    */
     void   *stream;               /* hipStream_t to run on; NULL = a library-owned stream      */
+    int32_t profile;              /* 1: time every range-pass launch with HIP events on `stream` */
+    int32_t reserved;             /* must be 0                                                 */
 } bm_options;
 
 typedef struct {
@@ -104,6 +106,9 @@ typedef struct {
     int64_t candidates;           /* candidates gathered over all blocks                       */
     int32_t path;                 /* path actually used                                        */
     int32_t block;                /* block size actually used                                  */
+    double  ms_range_kernel;      /* summed durations of the range-pass launches (profile = 1) */
+    int64_t range_launches;       /* range-pass launches                                       */
+    int64_t range_pairs;          /* landmark-point pairs they evaluated                       */
 } bm_stats;
 
 typedef struct {

@@ -76,7 +76,13 @@ def configure(lib):
     lib.bmo_separation.restype = f64
     lib.bmo_free.argtypes = [P(_Result)]
     lib.bmo_free.restype = None
+    lib.bmo_threads.restype = ctypes.c_int
     return lib
+
+
+def threads() -> int:
+    """OpenMP threads the oracle uses."""
+    return int(_load().bmo_threads())
 
 
 @dataclass

@@ -468,6 +468,15 @@ double bmo_separation(const void *pts, int64_t n, int32_t d, int32_t dtype,
     return sqrt(best);
 }
 
+int bmo_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 void bmo_free(bmo_result *r)
 {
     if (!r) return;

@@ -74,6 +74,9 @@ double bmo_covering_radius(const void *pts, int64_t n, int32_t d, int32_t dtype,
 double bmo_separation(const void *pts, int64_t n, int32_t d, int32_t dtype,
                       const int32_t *landmarks, int64_t n_landmarks);
 
+/* OpenMP threads the oracle runs with. */
+int bmo_threads(void);
+
 void bmo_free(bmo_result *r);
 
 #ifdef __cplusplus

@@ -38,7 +38,8 @@ class Options(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("refine", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("points_on_device", ctypes.c_int32),
                 ("results_on_device", ctypes.c_int32), ("max_device_bytes", ctypes.c_int64),
-                ("init_member_capacity", ctypes.c_int64), ("stream", ctypes.c_void_p)]
+                ("init_member_capacity", ctypes.c_int64), ("stream", ctypes.c_void_p),
+                ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -46,7 +47,8 @@ class Stats(ctypes.Structure):
                 ("ms_csr", ctypes.c_double), ("ms_edges", ctypes.c_double), ("ms_download", ctypes.c_double),
                 ("pairs_useful", ctypes.c_int64), ("pairs_issued", ctypes.c_int64),
                 ("band_pairs", ctypes.c_int64), ("blocks", ctypes.c_int64), ("candidates", ctypes.c_int64),
-                ("path", ctypes.c_int32), ("block", ctypes.c_int32)]
+                ("path", ctypes.c_int32), ("block", ctypes.c_int32), ("ms_range_kernel", ctypes.c_double),
+                ("range_launches", ctypes.c_int64), ("range_pairs", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -237,7 +239,7 @@ def _points(points):
 
 
 def options(path="auto", refine=True, block=0, device=-1, results_on_device=False, max_device_bytes=0,
-            init_member_capacity=0, stream=None, points_on_device=0) -> Options:
+            init_member_capacity=0, stream=None, points_on_device=0, profile=False) -> Options:
     o = Options()
     _check(load_library().bm_default_options(ctypes.byref(o)))
     o.path = PATHS[path] if isinstance(path, str) else int(path)
@@ -249,6 +251,7 @@ def options(path="auto", refine=True, block=0, device=-1, results_on_device=Fals
     o.max_device_bytes = int(max_device_bytes)
     o.init_member_capacity = int(init_member_capacity)
     o.stream = stream
+    o.profile = 1 if profile else 0
     return o
 
 

@@ -152,6 +152,7 @@ void check_common(const void *points, int64_t n, int32_t d, int32_t dtype, doubl
     if (o.block < 0 || o.block > 4096) fail(BM_EINVAL, "block must be 0 (automatic) or 1..4096");
     if (o.max_device_bytes < 0 || o.init_member_capacity < 0) fail(BM_EINVAL, "negative size option");
     if (o.path == BM_PATH_F16 && dtype != BM_F16) fail(BM_EINVAL, "path F16 needs float16 storage");
+    if ((o.profile != 0 && o.profile != 1) || o.reserved != 0) fail(BM_EINVAL, "bad profile/reserved option");
 }
 
 bool host_all_finite(const void *points, int64_t count, int32_t dtype)
@@ -358,79 +359,150 @@ bm_result *run_job(const Job &job, const bm_options &o)
                                      : (unsigned long long)std::max<int64_t>(2 * n, 1 << 16);
         uint64_t *keys = dev.alloc<uint64_t>(cap);
         GreedyState *st = dev.zeros<GreedyState>(1);
-        int32_t *lm_d = dev.alloc<int32_t>((size_t)std::max<int64_t>(job.fixed ? job.n_fixed : n, 1));
+        const int64_t lm_cap = std::max<int64_t>(job.fixed ? job.n_fixed : n, 1);
+        int32_t *lm_d = dev.alloc<int32_t>((size_t)lm_cap);
+        int32_t *lm_rank = job.fixed ? lm_d : dev.alloc<int32_t>((size_t)lm_cap);   // fixed mode: ranks = indices
         int32_t *A = dev.alloc<int32_t>((size_t)B);
+        int64_t *fixtab = dev.alloc<int64_t>(2 * (size_t)kBlockLogSize);
         GreedyState hs{};
         int64_t L = 0;
         RangeOut ro{nullptr, keys, cap, st, bn};
 
-        auto run_range = [&](int64_t ord0, const int32_t *na_dev) {
+        // range-pass launches, optionally bracketed by events on the same stream
+        std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
+        struct EvGuard {
+            std::vector<std::pair<hipEvent_t, hipEvent_t>> &v;
+            ~EvGuard()
+            {
+                for (auto &e : v) {
+                    (void)hipEventDestroy(e.first);
+                    (void)hipEventDestroy(e.second);
+                }
+            }
+        } ev_guard{evs};
+        auto run_range = [&](const int32_t *Alist, const int64_t *blk, uint64_t *covered) {
             ro.keys = keys;
             ro.cap = cap;
+            ro.covered = covered;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (o.profile) {
+                hip_ok(hipEventCreate(&e0), "hipEventCreate");
+                hip_ok(hipEventCreate(&e1), "hipEventCreate");
+                evs.emplace_back(e0, e1);
+                hip_ok(hipEventRecord(e0, dev.s), "hipEventRecord");
+            }
             if (path == BM_PATH_FP32)
-                hip_ok(launch_range_fp32(xf, P, e2, thr32, o.refine, A, na_dev, B, ord0, ro, dev.s), "range_fp32");
+                hip_ok(launch_range_fp32(xf, P, e2, thr32, o.refine, Alist, blk, B, ro, dev.s), "range_fp32");
             else
-                hip_ok(launch_range_mfma(ma, P, e2, A, na_dev, B, ord0, ro, dev.s), "range_mfma");
+                hip_ok(launch_range_mfma(ma, P, e2, Alist, blk, B, ro, dev.s), "range_mfma");
+            if (o.profile) hip_ok(hipEventRecord(e1, dev.s), "hipEventRecord");
+            res->stats.range_launches++;
         };
-        // grow the key buffer if the last block overflowed it, then redo that block's
-        // range pass (covered bits are idempotent ORs, so only the keys change)
-        auto regrow_if_needed = [&](unsigned long long before, int64_t ord0, const int32_t *na_dev) {
-            hs = dev.fetch(st);
-            if (hs.nkeys <= cap) return;
-            unsigned long long ncap = std::max<unsigned long long>(2 * cap, hs.nkeys + hs.nkeys / 2);
+        // The key buffer overflowed: grow it, then recompute the memberships of
+        // the landmark ranges [L0_j, L0_j + na_j) from the first incomplete one on,
+        // restarting the key counter where that block began.  The landmark set is
+        // unaffected (covered bits do not depend on the key buffer).
+        int64_t *tab_h = (int64_t *)((char *)dev.pinned + 2048);
+        auto refill = [&](const std::vector<BlockLog> &logs) {
+            const unsigned long long need = hs.nkeys;
+            const unsigned long long start = logs.front().nkeys_before;
+            const unsigned long long ncap = std::max<unsigned long long>(2 * cap, need + need / 2);
             uint64_t *nk = dev.alloc<uint64_t>(ncap);
-            if (before) hip_ok(hipMemcpyAsync(nk, keys, before * 8, hipMemcpyDeviceToDevice, dev.s), "regrow copy");
+            if (start) hip_ok(hipMemcpyAsync(nk, keys, start * 8, hipMemcpyDeviceToDevice, dev.s), "regrow copy");
+            dev.sync();
             dev.release(keys);
             keys = nk;
             cap = ncap;
-            hip_ok(hipMemcpyAsync(&st->nkeys, &before, 8, hipMemcpyHostToDevice, dev.s), "reset nkeys");
-            run_range(ord0, na_dev);
-            hs = dev.fetch(st);
-            if (hs.nkeys > cap) fail(BM_EINTERNAL, "membership count changed on recompute");
+            std::memcpy(dev.pinned, &start, 8);
+            hip_ok(hipMemcpyAsync(&st->nkeys, dev.pinned, 8, hipMemcpyHostToDevice, dev.s), "reset nkeys");
+            for (size_t j = 0; j < logs.size(); j += 64) {
+                const size_t m = std::min<size_t>(64, logs.size() - j);
+                dev.sync();
+                for (size_t q = 0; q < m; ++q) {
+                    tab_h[2 * q] = logs[j + q].L0;
+                    tab_h[2 * q + 1] = logs[j + q].na;
+                }
+                hip_ok(hipMemcpyAsync(fixtab, tab_h, m * 16, hipMemcpyHostToDevice, dev.s), "upload table");
+                for (size_t q = 0; q < m; ++q) run_range(lm_rank + logs[j + q].L0, fixtab + 2 * q, nullptr);
+            }
+            const GreedyState chk = dev.fetch(st);
+            if (chk.nkeys != need) fail(BM_EINTERNAL, "membership count changed on recompute");
+            hs.nkeys = chk.nkeys;
         };
 
         if (job.fixed) {
             // fixed-landmark mode: landmarks given as original indices (identity order)
             L = job.n_fixed;
             if (L > 0) hip_ok(hipMemcpyAsync(lm_d, job.fixed, (size_t)L * 4, hipMemcpyHostToDevice, dev.s), "upload lm");
-            int32_t *na_d = dev.alloc<int32_t>(1);
-            for (int64_t a0 = 0; a0 < L; a0 += B) {
-                const int32_t na = (int32_t)std::min<int64_t>(B, L - a0);
-                hip_ok(hipMemcpyAsync(A, job.fixed + a0, (size_t)na * 4, hipMemcpyHostToDevice, dev.s), "upload A");
-                hip_ok(hipMemcpyAsync(na_d, &na, 4, hipMemcpyHostToDevice, dev.s), "upload na");
-                const unsigned long long before = hs.nkeys;
-                run_range(a0, na_d);
-                regrow_if_needed(before, a0, na_d);
-                res->stats.pairs_issued += (int64_t)na * n;
-                res->stats.blocks++;
+            std::vector<BlockLog> all;
+            for (int64_t a0 = 0; a0 < L; a0 += B) all.push_back(BlockLog{a0, std::min<int64_t>(B, L - a0), 0});
+            std::vector<BlockLog> pending;
+            for (size_t j = 0; j < all.size(); j += 64) {
+                const size_t m = std::min<size_t>(64, all.size() - j);
+                dev.sync();
+                for (size_t q = 0; q < m; ++q) {
+                    tab_h[2 * q] = all[j + q].L0;
+                    tab_h[2 * q + 1] = all[j + q].na;
+                }
+                hip_ok(hipMemcpyAsync(fixtab, tab_h, m * 16, hipMemcpyHostToDevice, dev.s), "upload table");
+                for (size_t q = 0; q < m; ++q) run_range(lm_d + all[j + q].L0, fixtab + 2 * q, nullptr);
             }
+            hs = dev.fetch(st);
+            if (hs.nkeys > cap) refill(all);    // all[0].nkeys_before = 0: recompute everything
+            res->stats.blocks = (int64_t)all.size();
+            res->stats.pairs_issued = L * n;
         } else if (n > 0) {
             const int nw = (B + 63) / 64;
             uint64_t *covered = dev.zeros<uint64_t>((size_t)((n + 63) / 64));
             int32_t *cand = dev.alloc<int32_t>((size_t)B);
             uint64_t *C = dev.alloc<uint64_t>((size_t)B * nw);
-            ro.covered = covered;
+            BlockLog *blog = dev.alloc<BlockLog>(kBlockLogSize);
+            std::vector<BlockLog> blog_h(kBlockLogSize);
+            // Blocks are queued back to back; the host looks at the state once per batch.
+            int batch = 4;
             for (;;) {
-                const unsigned long long before = hs.nkeys;
-                hip_ok(launch_gather(covered, n, st, B, cand, dev.s), "gather");
-                hip_ok(launch_resolve_exact(P, e2, cand, st, B, C, dev.s), "resolve");
-                hip_ok(launch_accept(C, cand, st, B, A, lm_d + L, perm_d, dev.s), "accept");
-                run_range(L, &st->na);
-                regrow_if_needed(before, L, &st->na);
-                if (hs.nc == 0) break;
-                res->stats.blocks++;
-                res->stats.candidates += hs.nc;
-                res->stats.pairs_issued += (int64_t)hs.nc * (hs.nc - 1) / 2 + (int64_t)hs.na * n;
-                L += hs.na;
-                if (hs.cursor >= n && hs.nc < B) {
-                    // the gather reached the end; one more gather would find nothing
-                    break;
+                const unsigned long long blocks_before = hs.blocks;
+                for (int k = 0; k < batch; ++k) {
+                    hip_ok(launch_gather(covered, n, st, B, cand, dev.s), "gather");
+                    hip_ok(launch_resolve_exact(P, e2, cand, st, B, C, dev.s), "resolve");
+                    hip_ok(launch_accept(C, cand, st, B, A, lm_d, lm_rank, blog, perm_d, dev.s), "accept");
+                    run_range(A, &st->L0, covered);
                 }
+                hs = dev.fetch(st);
+                if (hs.nkeys > cap) {
+                    hip_ok(hipMemcpy(blog_h.data(), blog, sizeof(BlockLog) * kBlockLogSize, hipMemcpyDeviceToHost),
+                           "read block log");
+                    std::vector<BlockLog> logs;
+                    for (unsigned long long b = blocks_before; b < hs.blocks; ++b)
+                        logs.push_back(blog_h[b % kBlockLogSize]);
+                    // first block whose keys did not all fit
+                    size_t first = 0;
+                    while (first < logs.size()) {
+                        const unsigned long long end =
+                            first + 1 < logs.size() ? logs[first + 1].nkeys_before : hs.nkeys;
+                        if (end > cap) break;
+                        ++first;
+                    }
+                    if (first == logs.size()) fail(BM_EINTERNAL, "overflow not attributed to a block");
+                    refill(std::vector<BlockLog>(logs.begin() + (long)first, logs.end()));
+                }
+                if (hs.done) break;
+                batch = std::min(batch * 2, 64);
             }
+            L = hs.L;
+            res->stats.blocks = (int64_t)hs.blocks;
+            res->stats.candidates = (int64_t)hs.candidates;
+            res->stats.pairs_issued = (int64_t)hs.resolve_pairs + L * n;
         }
         dev.sync();
+        for (auto &e : evs) {
+            float ms = 0.f;
+            hip_ok(hipEventElapsedTime(&ms, e.first, e.second), "hipEventElapsedTime");
+            res->stats.ms_range_kernel += ms;
+        }
         res->stats.band_pairs = (int64_t)hs.band;
         res->stats.pairs_useful = L * n;
+        res->stats.range_pairs = L * n;
         res->stats.ms_greedy = ms_since(t_greedy);
 
         // -- membership CSR

@@ -16,15 +16,30 @@ struct PointsView {
     const int32_t *perm;
 };
 
-// Per-block state of the greedy, written by the kernels, read back by the host.
+// State of the greedy, kept on the device so blocks can be queued back to
+// back; the host reads it once per batch of blocks.
 struct GreedyState {
     int64_t cursor;                 // every rank < cursor is a landmark or covered
+    int64_t L0;                     // ordinal of this block's first landmark   } read by the range
+    int64_t na;                     // candidates accepted in this block         } pass as blk[0..1]
+    int64_t L;                      // landmarks so far
     int32_t nc;                     // candidates gathered in this block
-    int32_t na;                     // candidates accepted in this block
+    int32_t done;                   // 1 once a gather found no uncovered rank
     unsigned long long nkeys;       // membership keys appended so far
     unsigned long long band;        // pairs the filter sent to the FP64 recheck
     unsigned long long rounds;      // acceptance rounds (diagnostic)
+    unsigned long long blocks;      // blocks with at least one candidate
+    unsigned long long candidates;  // candidates over all blocks
+    unsigned long long resolve_pairs;
 };
+
+// Per-block record for recomputing a block's memberships after the key
+// buffer overflowed: its first ordinal, accepted count and key count before it.
+struct BlockLog {
+    int64_t L0, na;
+    unsigned long long nkeys_before;
+};
+constexpr int kBlockLogSize = 256;
 
 // Decision thresholds of the plain FP32 filter (direct difference):
 // s32 <  lo  => member for sure;  s32 >= hi => non-member for sure; else band.

@@ -60,6 +60,12 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(const uint64_t *cover
         st->nc = count;
         st->na = 0;
         st->cursor = (count == B) ? sh_cursor : n;
+        if (count == 0) st->done = 1;
+        else {
+            st->blocks += 1;
+            st->candidates += (unsigned long long)count;
+            st->resolve_pairs += (unsigned long long)count * (unsigned long long)(count - 1) / 2;
+        }
     }
 }
 
@@ -104,9 +110,10 @@ constexpr int ACCEPT_THREADS = 1024;
 constexpr int MAX_B = 4096;
 
 __global__ __launch_bounds__(ACCEPT_THREADS) void k_accept(const uint64_t *C, int nw, const int32_t *cand,
-                                                           GreedyState *st, int32_t *A, int32_t *lm_out,
-                                                           const int32_t *perm)
+                                                           GreedyState *st, int32_t *A, int32_t *landmarks,
+                                                           int32_t *lm_rank, BlockLog *blog, const int32_t *perm)
 {
+    const int64_t L0 = st->L;
     __shared__ unsigned long long acc[MAX_B / 64], rej[MAX_B / 64];
     __shared__ int sh_undecided, sh_scan[ACCEPT_THREADS / 64];
     const int nc = st->nc;
@@ -150,21 +157,30 @@ __global__ __launch_bounds__(ACCEPT_THREADS) void k_accept(const uint64_t *C, in
         if ((acc[j >> 6] >> (j & 63)) & 1ull) {
             const int32_t r = cand[j];
             A[pos] = r;
-            lm_out[pos] = perm ? perm[r] : r;
+            landmarks[L0 + pos] = perm ? perm[r] : r;
+            lm_rank[L0 + pos] = r;
             ++pos;
         }
     }
     if (threadIdx.x == 0) {
+        st->L0 = L0;
         st->na = total;
+        st->L = L0 + total;
         st->rounds += rounds;
+        if (nc > 0) {
+            BlockLog &b = blog[(st->blocks - 1) % kBlockLogSize];
+            b.L0 = L0;
+            b.na = total;
+            b.nkeys_before = st->nkeys;
+        }
     }
 }
 
 hipError_t launch_accept(const uint64_t *C, const int32_t *cand, GreedyState *st, int B, int32_t *A,
-                         int32_t *landmarks_out, const int32_t *perm, hipStream_t s)
+                         int32_t *landmarks, int32_t *lm_rank, BlockLog *blog, const int32_t *perm, hipStream_t s)
 {
     if (B > MAX_B) return hipErrorInvalidValue;
-    k_accept<<<1, ACCEPT_THREADS, 0, s>>>(C, (B + 63) / 64, cand, st, A, landmarks_out, perm);
+    k_accept<<<1, ACCEPT_THREADS, 0, s>>>(C, (B + 63) / 64, cand, st, A, landmarks, lm_rank, blog, perm);
     return hipGetLastError();
 }
 

@@ -30,13 +30,16 @@ hipError_t launch_gather(const uint64_t *covered, int64_t n, GreedyState *st, in
                          hipStream_t s);
 hipError_t launch_resolve_exact(const PointsView &P, double e2, const int32_t *cand, const GreedyState *st,
                                 int B, uint64_t *C, hipStream_t s);
+// Accepts in rank order; appends to landmarks (original indices) and lm_rank
+// at ordinal st->L, and records the block in blog[st->blocks % kBlockLogSize].
 hipError_t launch_accept(const uint64_t *C, const int32_t *cand, GreedyState *st, int B, int32_t *A,
-                         int32_t *landmarks_out, const int32_t *perm, hipStream_t s);
+                         int32_t *landmarks, int32_t *lm_rank, BlockLog *blog, const int32_t *perm, hipStream_t s);
 
 // ---- range passes -----------------------------------------------------------------------
-// Fixed-landmark or greedy range pass: landmarks A[0..*na) (ranks), ordinals
-// ord0 + i.  Members are appended as keys (ordinal << bn | original index) and
-// their covered bits set.
+// Range pass of landmarks A[0..blk[1]) (ranks) with ordinals blk[0] + i;
+// blk points to device memory (the greedy state's L0/na, or a fixed table).
+// Members are appended as keys (ordinal << bn | original index) and their
+// covered bits set.
 struct RangeOut {
     uint64_t *covered;              // rank-order bitmap, may be null (fixed-landmark mode)
     uint64_t *keys;
@@ -46,13 +49,13 @@ struct RangeOut {
 };
 
 hipError_t launch_range_fp32(const float *xf, const PointsView &P, double e2, Fp32Thresholds thr,
-                             int refine, const int32_t *A, const int32_t *na_dev, int na_max,
-                             int64_t ord0, const RangeOut &o, hipStream_t s);
+                             int refine, const int32_t *A, const int64_t *blk, int na_max,
+                             const RangeOut &o, hipStream_t s);
 
 // One-wave check of the matrix-core layout and subnormal handling (flags, see range_mfma.hip).
 hipError_t run_selfcheck(int *flags_dev, hipStream_t s);
 hipError_t launch_range_mfma(const MfmaArgs &a, const PointsView &P, double e2, const int32_t *A,
-                             const int32_t *na_dev, int na_max, int64_t ord0, const RangeOut &o, hipStream_t s);
+                             const int64_t *blk, int na_max, const RangeOut &o, hipStream_t s);
 
 // ---- membership CSR (csr.hip) -------------------------------------------------------------
 hipError_t sort_keys(void *tmp, size_t *tmp_bytes, const uint64_t *in, uint64_t *out, size_t count,

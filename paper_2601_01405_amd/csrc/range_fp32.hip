@@ -18,11 +18,12 @@ constexpr int RF_KC = 32;      // coordinates per chunk
 __global__ __launch_bounds__(RF_THREADS) void k_range_fp32(const float *__restrict__ xf, PointsView P, double e2,
                                                            Fp32Thresholds thr, int refine,
                                                            const int32_t *__restrict__ A,
-                                                           const int32_t *na_dev, int64_t ord0, RangeOut o)
+                                                           const int64_t *blk, RangeOut o)
 {
     __shared__ float lt[RF_LT][RF_KC];
     __shared__ int32_t lrank[RF_LT];
-    const int na = *na_dev;
+    const int64_t ord0 = blk[0];
+    const int na = (int)blk[1];
     const int d = P.d;
     const int64_t r = blockIdx.x * (int64_t)RF_THREADS + threadIdx.x;
     const bool valid = r < P.n;
@@ -96,13 +97,12 @@ __global__ __launch_bounds__(RF_THREADS) void k_range_fp32(const float *__restri
 }
 
 hipError_t launch_range_fp32(const float *xf, const PointsView &P, double e2, Fp32Thresholds thr, int refine,
-                             const int32_t *A, const int32_t *na_dev, int na_max, int64_t ord0,
-                             const RangeOut &o, hipStream_t s)
+                             const int32_t *A, const int64_t *blk, int na_max, const RangeOut &o, hipStream_t s)
 {
     (void)na_max;
     if (P.n <= 0) return hipSuccess;
     const int blocks = (int)((P.n + RF_THREADS - 1) / RF_THREADS);
-    k_range_fp32<<<blocks, RF_THREADS, 0, s>>>(xf, P, e2, thr, refine, A, na_dev, ord0, o);
+    k_range_fp32<<<blocks, RF_THREADS, 0, s>>>(xf, P, e2, thr, refine, A, blk, o);
     return hipGetLastError();
 }
 

@@ -177,10 +177,11 @@ constexpr int RM_THREADS = 256;
 // KS = K steps per chunk (all of K when nch == 1).
 template <int KS, int MP, bool F16>
 __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsView P, double e2,
-                                                           const int32_t *__restrict__ A, const int32_t *na_dev,
-                                                           int64_t ord0, RangeOut o, int NG, int64_t tpc, int nch)
+                                                           const int32_t *__restrict__ A, const int64_t *blk,
+                                                           RangeOut o, int NG, int64_t tpc, int nch)
 {
-    const int na = *na_dev;
+    const int64_t ord0 = blk[0];
+    const int na = (int)blk[1];
     const int lane = lane_id();
     const int col = lane & 31, half = lane >> 5;
     const int64_t wave = (int64_t)blockIdx.x * (RM_THREADS / 64) + (threadIdx.x >> 6);
@@ -379,8 +380,8 @@ hipError_t run_selfcheck(int *flags_dev, hipStream_t s)
 }
 
 template <int KS, int MP, bool F16>
-static hipError_t launch_ks(const MfmaArgs &a, const PointsView &P, double e2, const int32_t *A, const int32_t *na_dev,
-                            int na_max, int64_t ord0, const RangeOut &o, int nch, hipStream_t s)
+static hipError_t launch_ks(const MfmaArgs &a, const PointsView &P, double e2, const int32_t *A, const int64_t *blk,
+                            int na_max, const RangeOut &o, int nch, hipStream_t s)
 {
     const int npan = (na_max + 31) / 32;
     const int NG = (npan + MP - 1) / MP;
@@ -394,34 +395,34 @@ static hipError_t launch_ks(const MfmaArgs &a, const PointsView &P, double e2, c
     chunks = (NT + tpc - 1) / tpc;
     const int64_t waves = (int64_t)NG * chunks;
     const int64_t blocks = (waves + 3) / 4;
-    k_range_mfma<KS, MP, F16><<<(unsigned)blocks, RM_THREADS, 0, s>>>(a, P, e2, A, na_dev, ord0, o, NG, tpc, nch);
+    k_range_mfma<KS, MP, F16><<<(unsigned)blocks, RM_THREADS, 0, s>>>(a, P, e2, A, blk, o, NG, tpc, nch);
     return hipGetLastError();
 }
 
 template <bool F16>
-static hipError_t dispatch(const MfmaArgs &a, const PointsView &P, double e2, const int32_t *A, const int32_t *na_dev,
-                           int na_max, int64_t ord0, const RangeOut &o, hipStream_t s)
+static hipError_t dispatch(const MfmaArgs &a, const PointsView &P, double e2, const int32_t *A, const int64_t *blk,
+                           int na_max, const RangeOut &o, hipStream_t s)
 {
     const int S = a.S;
     switch (S) {
-    case 1: return launch_ks<1, 2, F16>(a, P, e2, A, na_dev, na_max, ord0, o, 1, s);
-    case 2: return launch_ks<2, 2, F16>(a, P, e2, A, na_dev, na_max, ord0, o, 1, s);
-    case 3: return launch_ks<3, 2, F16>(a, P, e2, A, na_dev, na_max, ord0, o, 1, s);
-    case 4: return launch_ks<4, 2, F16>(a, P, e2, A, na_dev, na_max, ord0, o, 1, s);
-    case 5: return launch_ks<5, 2, F16>(a, P, e2, A, na_dev, na_max, ord0, o, 1, s);
-    case 6: return launch_ks<6, 2, F16>(a, P, e2, A, na_dev, na_max, ord0, o, 1, s);
-    case 7: return launch_ks<7, 2, F16>(a, P, e2, A, na_dev, na_max, ord0, o, 1, s);
-    case 8: return launch_ks<8, 2, F16>(a, P, e2, A, na_dev, na_max, ord0, o, 1, s);
-    default: return launch_ks<8, 2, F16>(a, P, e2, A, na_dev, na_max, ord0, o, (S + 7) / 8, s);
+    case 1: return launch_ks<1, 2, F16>(a, P, e2, A, blk, na_max, o, 1, s);
+    case 2: return launch_ks<2, 2, F16>(a, P, e2, A, blk, na_max, o, 1, s);
+    case 3: return launch_ks<3, 2, F16>(a, P, e2, A, blk, na_max, o, 1, s);
+    case 4: return launch_ks<4, 2, F16>(a, P, e2, A, blk, na_max, o, 1, s);
+    case 5: return launch_ks<5, 2, F16>(a, P, e2, A, blk, na_max, o, 1, s);
+    case 6: return launch_ks<6, 2, F16>(a, P, e2, A, blk, na_max, o, 1, s);
+    case 7: return launch_ks<7, 2, F16>(a, P, e2, A, blk, na_max, o, 1, s);
+    case 8: return launch_ks<8, 2, F16>(a, P, e2, A, blk, na_max, o, 1, s);
+    default: return launch_ks<8, 2, F16>(a, P, e2, A, blk, na_max, o, (S + 7) / 8, s);
     }
 }
 
 hipError_t launch_range_mfma(const MfmaArgs &a, const PointsView &P, double e2, const int32_t *A,
-                             const int32_t *na_dev, int na_max, int64_t ord0, const RangeOut &o, hipStream_t s)
+                             const int64_t *blk, int na_max, const RangeOut &o, hipStream_t s)
 {
     if (P.n <= 0 || na_max <= 0) return hipSuccess;
-    if (a.kind == MFMA_F16) return dispatch<true>(a, P, e2, A, na_dev, na_max, ord0, o, s);
-    return dispatch<false>(a, P, e2, A, na_dev, na_max, ord0, o, s);
+    if (a.kind == MFMA_F16) return dispatch<true>(a, P, e2, A, blk, na_max, o, s);
+    return dispatch<false>(a, P, e2, A, blk, na_max, o, s);
 }
 
 } // namespace bm

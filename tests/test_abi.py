@@ -4,6 +4,7 @@ before touching a device."""
 import ctypes
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -29,11 +30,26 @@ def test_library_exports_every_declared_function():
     assert lib.bm_abi_version() == 1
 
 
-def test_struct_layouts_match_header():
-    # the ctypes mirrors must have the C sizes (natural alignment, LP64)
-    assert ctypes.sizeof(bm.Options) == 4 * 6 + 8 * 2 + 8
-    assert ctypes.sizeof(bm.Stats) == 8 * 6 + 8 * 5 + 4 * 2
-    assert ctypes.sizeof(bm.Problem) == 8 + 8 + 4 + 4 + 8 + 8 + 8
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors have the sizes and field offsets the C compiler gives bm.h."""
+    mirrors = {"bm_options": bm.Options, "bm_stats": bm.Stats, "bm_result": bm._Result,
+               "bm_problem": bm.Problem, "bm_bound": bm.Bound}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bm.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 def test_default_options():

@@ -152,11 +152,13 @@ def test_results_on_device_and_torch_input():
 
 
 @pytest.mark.parametrize("path", EXACT_PATHS)
-def test_fixed_landmarks(path):
+@pytest.mark.parametrize("cap", [0, 1])
+def test_fixed_landmarks(path, cap):
     x = W.clusters(3000, 12, k=4, box=5.0, seed=6, dtype=np.float32)
     lm = np.random.default_rng(0).choice(3000, 200, replace=False).astype(np.int32)
-    say("fixed landmarks n=3000 L=200", path)
-    assert_same(bm.range_sets(x, lm, 3.0, path=path), oracle.range_sets(x, lm, 3.0), "fixed")
+    say("fixed landmarks n=3000 L=200", path, "cap", cap)
+    got = bm.range_sets(x, lm, 3.0, path=path, init_member_capacity=cap, block=64)
+    assert_same(got, oracle.range_sets(x, lm, 3.0), "fixed")
 
 
 def test_build_many_matches_single():
