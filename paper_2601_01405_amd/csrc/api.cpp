@@ -249,8 +249,10 @@ int auto_block(int64_t n, int path)
 // three-product split; float16 storage is exact in f16.
 int auto_path(int dtype, int d, double e2, double max_nu, double max_abs)
 {
-    if (dtype == BM_F16) return BM_PATH_F16;
+    if (dtype == BM_F16 && (d + 15) / 16 <= kMaxMfmaSteps) return BM_PATH_F16;
     const int K1 = (d + 15) / 16 * 16;
+    if (K1 / 16 > kMaxMfmaSteps) return BM_PATH_FP32;            // beyond the MFMA kernel's K
+    if ((3 * d + 15) / 16 > kMaxMfmaSteps) return BM_PATH_BF16;
     const MfmaBound b1 = mfma_bound(MFMA_BF16, d, K1, e2, std::sqrt(max_nu), max_abs, false);
     const double half_width = 2.0 * ((b1.alpha + b1.beta) * max_nu + b1.abs_err);   // in D units
     return half_width <= 0.02 * e2 ? BM_PATH_BF16 : BM_PATH_BF16X3;
@@ -325,8 +327,8 @@ bm_result *run_job(const Job &job, const bm_options &o)
             const int kind = path;   // BM_PATH_BF16/BF16X3/F16 share the MfmaKind values
             const int Kraw = (kind == MFMA_BF16X3) ? 3 * d : d;
             const int S = (Kraw + 15) / 16;
-            const int64_t NT = (n + 31) / 32;
-            const size_t words = (size_t)NT * S * 64 * 8;
+            if (S > kMaxMfmaSteps) fail(BM_EINVAL, "d too large for this MFMA path (use FP32, or BF16 for d <= 480)");
+            const size_t words = mfma_operand_words(n, S);
             uint16_t *Pop = dev.alloc<uint16_t>(words);
             uint16_t *Qop = (kind == MFMA_BF16X3) ? dev.alloc<uint16_t>(words) : Pop;
             hip_ok(launch_mfma_operands(P, kind, S, Pop, Qop, dev.s), "mfma_operands");
@@ -456,6 +458,25 @@ bm_result *run_job(const Job &job, const bm_options &o)
             uint64_t *covered = dev.zeros<uint64_t>((size_t)((n + 63) / 64));
             int32_t *cand = dev.alloc<int32_t>((size_t)B);
             uint64_t *C = dev.alloc<uint64_t>((size_t)B * nw);
+            int *rowflag = dev.alloc<int>((size_t)B);
+            // packed candidate set for the matrix-core resolve
+            MfmaArgs pk = ma;
+            int32_t *cand_orig = nullptr;
+            const bool mfma_resolve = path != BM_PATH_FP32;
+            if (mfma_resolve) {
+                const int64_t Bp = (B + 31) / 32 * 32;
+                const size_t words = mfma_operand_words(Bp, ma.S);
+                pk.Pop = dev.alloc<uint16_t>(words);
+                pk.Qop = (ma.Qop != ma.Pop) ? dev.alloc<uint16_t>(words) : pk.Pop;
+                float *psc = dev.alloc<float>((size_t)Bp * 5);
+                pk.cinit = psc;
+                pk.nuup = psc + Bp;
+                pk.U = psc + 2 * Bp;
+                pk.V = psc + 3 * Bp;
+                pk.Z = psc + 4 * Bp;
+                cand_orig = dev.alloc<int32_t>((size_t)Bp);
+            }
+            const PointsView Pc{Xd, B, d, job.dtype, cand_orig};
             BlockLog *blog = dev.alloc<BlockLog>(kBlockLogSize);
             std::vector<BlockLog> blog_h(kBlockLogSize);
             // Blocks are queued back to back; the host looks at the state once per batch.
@@ -463,12 +484,19 @@ bm_result *run_job(const Job &job, const bm_options &o)
             for (;;) {
                 const unsigned long long blocks_before = hs.blocks;
                 for (int k = 0; k < batch; ++k) {
-                    hip_ok(launch_gather(covered, n, st, B, cand, dev.s), "gather");
-                    hip_ok(launch_resolve_exact(P, e2, cand, st, B, C, dev.s), "resolve");
-                    hip_ok(launch_accept(C, cand, st, B, A, lm_d, lm_rank, blog, perm_d, dev.s), "accept");
+                    hip_ok(launch_gather(covered, n, st, B, cand, rowflag, dev.s), "gather");
+                    if (mfma_resolve) {
+                        hip_ok(launch_pack_candidates(ma, cand, st, perm_d, B, pk, cand_orig, dev.s), "pack");
+                        hip_ok(launch_resolve_mfma(pk, Pc, &st->nc, e2, B, (uint32_t *)C, rowflag, st, dev.s),
+                               "resolve_mfma");
+                    } else {
+                        hip_ok(launch_resolve_exact(P, e2, cand, st, B, C, rowflag, dev.s), "resolve");
+                    }
+                    hip_ok(launch_accept(C, rowflag, cand, st, B, A, lm_d, lm_rank, blog, perm_d, dev.s), "accept");
                     run_range(A, &st->L0, covered);
                 }
                 hs = dev.fetch(st);
+                if (hs.error) fail(BM_EINTERNAL, "candidate acceptance did not converge");
                 if (hs.nkeys > cap) {
                     hip_ok(hipMemcpy(blog_h.data(), blog, sizeof(BlockLog) * kBlockLogSize, hipMemcpyDeviceToHost),
                            "read block log");

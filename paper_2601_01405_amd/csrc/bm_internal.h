@@ -25,6 +25,8 @@ struct GreedyState {
     int64_t L;                      // landmarks so far
     int32_t nc;                     // candidates gathered in this block
     int32_t done;                   // 1 once a gather found no uncovered rank
+    int32_t error;                  // 1 if the acceptance rounds did not converge
+    int32_t pad_;
     unsigned long long nkeys;       // membership keys appended so far
     unsigned long long band;        // pairs the filter sent to the FP64 recheck
     unsigned long long rounds;      // acceptance rounds (diagnostic)
@@ -56,6 +58,14 @@ struct Fp32Thresholds {
 // [hi | hi | lo] and the landmark side [hi | lo | hi], so their dot product is
 // hi.hi + hi.lo + lo.hi.
 enum MfmaKind { MFMA_BF16 = 2, MFMA_BF16X3 = 3, MFMA_F16 = 4 };
+constexpr int kMaxMfmaSteps = 30;           // K <= 480: d <= 480 (one product) or 160 (three)
+
+// 16-bit words of a swizzled operand array for `points` points and S steps:
+// ceil(points / 32) tiles x S steps x 64 lanes x 8 values.
+inline size_t mfma_operand_words(int64_t points, int S)
+{
+    return (size_t)((points + 31) / 32) * (size_t)S * 64 * 8;
+}
 
 // Constants of the MFMA error bound (host computed, see bounds.h).  The kernel
 // output for landmark a and point x is  G = -RN32(nu_a)/2 + sum_k P_k Q_k, an

@@ -27,7 +27,7 @@ __device__ __forceinline__ int64_t orig_index(const PointsView &P, int64_t rank)
 // partial sum reaches e2 the loop stops: every term is >= 0 and rounded addition
 // is monotone, so the full sum would not be below e2 either.
 template <int DT>
-__device__ __attribute__((noinline)) bool exact_member_t(const void *X, int32_t d, int64_t a, int64_t b,
+__device__ __forceinline__ bool exact_member_t(const void *X, int32_t d, int64_t a, int64_t b,
                                                          double e2)
 {
 #pragma clang fp contract(off)

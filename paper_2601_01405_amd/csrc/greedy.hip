@@ -18,8 +18,9 @@ constexpr int GATHER_THREADS = 1024;
 // One workgroup: scans the covered bitmap from the cursor, 64 ranks per thread
 // per sweep, and lists up to B uncovered ranks in increasing order.
 __global__ __launch_bounds__(GATHER_THREADS) void k_gather(const uint64_t *covered, int64_t n,
-                                                           GreedyState *st, int B, int32_t *cand)
+                                                           GreedyState *st, int B, int32_t *cand, int *rowflag)
 {
+    for (int j = threadIdx.x; j < B; j += GATHER_THREADS) rowflag[j] = 0;
     __shared__ int sh_scan[GATHER_THREADS / 64];
     __shared__ int64_t sh_cursor;
     const int64_t nwords = (n + 63) >> 6;
@@ -70,16 +71,16 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(const uint64_t *cover
 }
 
 hipError_t launch_gather(const uint64_t *covered, int64_t n, GreedyState *st, int B, int32_t *cand,
-                         hipStream_t s)
+                         int *rowflag, hipStream_t s)
 {
-    k_gather<<<1, GATHER_THREADS, 0, s>>>(covered, n, st, B, cand);
+    k_gather<<<1, GATHER_THREADS, 0, s>>>(covered, n, st, B, cand, rowflag);
     return hipGetLastError();
 }
 
 // Conflict words: C[j * nw + w] bit i' = 1 iff candidate i = 64 w + i' < j and
 // cand[i] has cand[j] in its ball.  One wave per (row j, word w) with 64 w < j.
 __global__ __launch_bounds__(256) void k_resolve_exact(PointsView P, double e2, const int32_t *cand,
-                                                       const GreedyState *st, int nw, uint64_t *C)
+                                                       const GreedyState *st, int nw, uint64_t *C, int *rowflag)
 {
     const int nc = st->nc;
     const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
@@ -89,29 +90,34 @@ __global__ __launch_bounds__(256) void k_resolve_exact(PointsView P, double e2, 
     bool hit = false;
     if (i < j) hit = exact_member(P, orig_index(P, cand[i]), orig_index(P, cand[j]), e2);
     uint64_t m = __ballot(hit);
-    if (lane_id() == 0) C[(int64_t)j * nw + w] = m;
+    if (lane_id() == 0) {
+        C[(int64_t)j * nw + w] = m;
+        if (m) rowflag[j] = 1;
+    }
 }
 
 hipError_t launch_resolve_exact(const PointsView &P, double e2, const int32_t *cand, const GreedyState *st,
-                                int B, uint64_t *C, hipStream_t s)
+                                int B, uint64_t *C, int *rowflag, hipStream_t s)
 {
     const int nw = (B + 63) / 64;
     dim3 grid(nw, (B + 3) / 4);
-    k_resolve_exact<<<grid, 256, 0, s>>>(P, e2, cand, st, nw, C);
+    k_resolve_exact<<<grid, 256, 0, s>>>(P, e2, cand, st, nw, C, rowflag);
     return hipGetLastError();
 }
 
-// Acceptance in rank order, by rounds: a candidate is rejected as soon as one
-// of its earlier conflicts is accepted, and accepted once all of them are
-// rejected.  Decisions never change, so a stale view only delays one; the
+// Acceptance in rank order, by rounds: a candidate without any earlier
+// conflict (rowflag 0) is accepted at once; otherwise it is rejected as soon
+// as one of its earlier conflicts is accepted, and accepted once all of them
+// are rejected.  Decisions never change, so a stale view only delays one; the
 // earliest undecided candidate always has all its conflicts decided, so every
 // round decides at least one.  The result equals the sequential scan.
 constexpr int ACCEPT_THREADS = 1024;
 constexpr int MAX_B = 4096;
 
-__global__ __launch_bounds__(ACCEPT_THREADS) void k_accept(const uint64_t *C, int nw, const int32_t *cand,
-                                                           GreedyState *st, int32_t *A, int32_t *landmarks,
-                                                           int32_t *lm_rank, BlockLog *blog, const int32_t *perm)
+__global__ __launch_bounds__(ACCEPT_THREADS) void k_accept(const uint64_t *C, const int *rowflag, int nw,
+                                                           const int32_t *cand, GreedyState *st, int32_t *A,
+                                                           int32_t *landmarks, int32_t *lm_rank, BlockLog *blog,
+                                                           const int32_t *perm)
 {
     const int64_t L0 = st->L;
     __shared__ unsigned long long acc[MAX_B / 64], rej[MAX_B / 64];
@@ -127,10 +133,15 @@ __global__ __launch_bounds__(ACCEPT_THREADS) void k_accept(const uint64_t *C, in
             const int wj = j >> 6;
             const unsigned long long bit = 1ull << (j & 63);
             if ((acc[wj] | rej[wj]) & bit) continue;
+            if (!rowflag[j]) {
+                atomicOr(&acc[wj], bit);
+                continue;
+            }
             bool any_acc = false, any_open = false;
             const int nwj = (j + 63) >> 6;       // words holding candidates < j
             for (int w = 0; w < nwj && !any_acc; ++w) {
                 unsigned long long c = C[(int64_t)j * nw + w];
+                if (w == wj) c &= bit - 1ull;     // only candidates i < j (the rest of the word is not written)
                 unsigned long long a = __atomic_load_n(&acc[w], __ATOMIC_RELAXED);
                 unsigned long long r = __atomic_load_n(&rej[w], __ATOMIC_RELAXED);
                 if (c & a) any_acc = true;
@@ -145,6 +156,10 @@ __global__ __launch_bounds__(ACCEPT_THREADS) void k_accept(const uint64_t *C, in
         const int und = sh_undecided;
         __syncthreads();
         if (!und) break;
+        if (rounds > (unsigned long long)nc) {   // every round decides one candidate: cannot happen
+            if (threadIdx.x == 0) st->error = 1;
+            break;
+        }
     }
     // compaction of the accepted candidates, in rank order
     int total = 0;
@@ -176,11 +191,12 @@ __global__ __launch_bounds__(ACCEPT_THREADS) void k_accept(const uint64_t *C, in
     }
 }
 
-hipError_t launch_accept(const uint64_t *C, const int32_t *cand, GreedyState *st, int B, int32_t *A,
-                         int32_t *landmarks, int32_t *lm_rank, BlockLog *blog, const int32_t *perm, hipStream_t s)
+hipError_t launch_accept(const uint64_t *C, const int *rowflag, const int32_t *cand, GreedyState *st, int B,
+                         int32_t *A, int32_t *landmarks, int32_t *lm_rank, BlockLog *blog, const int32_t *perm,
+                         hipStream_t s)
 {
     if (B > MAX_B) return hipErrorInvalidValue;
-    k_accept<<<1, ACCEPT_THREADS, 0, s>>>(C, (B + 63) / 64, cand, st, A, landmarks, lm_rank, blog, perm);
+    k_accept<<<1, ACCEPT_THREADS, 0, s>>>(C, rowflag, (B + 63) / 64, cand, st, A, landmarks, lm_rank, blog, perm);
     return hipGetLastError();
 }
 

@@ -26,14 +26,17 @@ hipError_t launch_mfma_scalars(int64_t n, const double *nu, const MfmaBound &b, 
                                float *nuup, float *U, float *V, float *Z, hipStream_t s);
 
 // ---- greedy (greedy.hip) ----------------------------------------------------------------
+// Lists up to B uncovered ranks after the cursor and clears rowflag[0..B).
 hipError_t launch_gather(const uint64_t *covered, int64_t n, GreedyState *st, int B, int32_t *cand,
-                         hipStream_t s);
+                         int *rowflag, hipStream_t s);
+// Conflict words of the candidate block with the FP64 predicate on every pair.
 hipError_t launch_resolve_exact(const PointsView &P, double e2, const int32_t *cand, const GreedyState *st,
-                                int B, uint64_t *C, hipStream_t s);
+                                int B, uint64_t *C, int *rowflag, hipStream_t s);
 // Accepts in rank order; appends to landmarks (original indices) and lm_rank
 // at ordinal st->L, and records the block in blog[st->blocks % kBlockLogSize].
-hipError_t launch_accept(const uint64_t *C, const int32_t *cand, GreedyState *st, int B, int32_t *A,
-                         int32_t *landmarks, int32_t *lm_rank, BlockLog *blog, const int32_t *perm, hipStream_t s);
+hipError_t launch_accept(const uint64_t *C, const int *rowflag, const int32_t *cand, GreedyState *st, int B,
+                         int32_t *A, int32_t *landmarks, int32_t *lm_rank, BlockLog *blog, const int32_t *perm,
+                         hipStream_t s);
 
 // ---- range passes -----------------------------------------------------------------------
 // Range pass of landmarks A[0..blk[1]) (ranks) with ordinals blk[0] + i;
@@ -56,6 +59,13 @@ hipError_t launch_range_fp32(const float *xf, const PointsView &P, double e2, Fp
 hipError_t run_selfcheck(int *flags_dev, hipStream_t s);
 hipError_t launch_range_mfma(const MfmaArgs &a, const PointsView &P, double e2, const int32_t *A,
                              const int64_t *blk, int na_max, const RangeOut &o, hipStream_t s);
+// Candidate-block resolve on the matrix cores: `packed` holds the candidates'
+// operands and scalars in candidate order, Pc.perm their original indices;
+// writes the conflict words (as 32-bit halves) and row flags.
+hipError_t launch_resolve_mfma(const MfmaArgs &packed, const PointsView &Pc, const int32_t *nc_dev, double e2, int B,
+                               uint32_t *C32, int *rowflag, GreedyState *st, hipStream_t s);
+hipError_t launch_pack_candidates(const MfmaArgs &a, const int32_t *cand, const GreedyState *st, const int32_t *perm,
+                                  int B, const MfmaArgs &out, int32_t *cand_orig, hipStream_t s);
 
 // ---- membership CSR (csr.hip) -------------------------------------------------------------
 hipError_t sort_keys(void *tmp, size_t *tmp_bytes, const uint64_t *in, uint64_t *out, size_t count,

@@ -16,6 +16,8 @@
 // is decided by the FP64 predicate (the verified range set of Sec. 5.3).
 // With refine = 0 the pair is a member iff G > Z_x = (|x|^2 - e2)/2: a
 // compressed-distance oracle with false negatives and false positives.
+#include <cstdlib>
+
 #include "dev_common.h"
 #include "kernels.h"
 
@@ -140,8 +142,13 @@ __global__ void k_mfma_scalars(int64_t n, const double *nu, MfmaBound b, double 
         U[r] = __builtin_nanf("");
         V[r] = __builtin_nanf("");
     } else {
-        U[r] = to_f32_down((v - b.t_out) * 0.5 - b.beta * v - b.abs_err - rel);
-        V[r] = to_f32_up((v - b.t_in) * 0.5 + b.beta * v + b.abs_err + rel);
+        // The kernel forms u = RN(U - w) and v = RN(V + w) with w >= alpha max|l|^2
+        // widened by 2^-22; taking U and V 2^-23 further out keeps u <= U_exact - w_exact
+        // and v >= V_exact + w_exact despite that rounding.
+        const double u = (v - b.t_out) * 0.5 - b.beta * v - b.abs_err - rel;
+        const double w = (v - b.t_in) * 0.5 + b.beta * v + b.abs_err + rel;
+        U[r] = to_f32_down(u - 0x1p-23 * fabs(u) * (1.0 + 1e-9));
+        V[r] = to_f32_up(w + 0x1p-23 * fabs(w) * (1.0 + 1e-9));
     }
     Z[r] = (float)((v - e2) * 0.5);
 }
@@ -171,53 +178,106 @@ __device__ __forceinline__ f32x16 mfma32(u32x4 a, u32x4 b, f32x16 c)
 // Row of the 32x32 output held in accumulator register i of this lane.
 __device__ __forceinline__ int acc_row(int i, int half) { return 8 * (i >> 2) + 4 * half + (i & 3); }
 
-constexpr int RM_THREADS = 256;
+// Work split.  A workgroup of RM_WAVES waves owns RM_WAVES * RM_MP landmark
+// panels of 32 (A operands and accumulator starts in registers for the whole
+// pass) and a contiguous range of 32-point tiles.  Each tile's B operands and
+// thresholds are staged once per workgroup in LDS (double buffered: the next
+// tile's global loads are in flight while the current one is multiplied), so a
+// point tile is read from memory once per RM_WAVES * RM_MP * 32 landmarks.
+//
+// MEMBERS mode appends (ordinal, point) keys and sets covered bits.  CONFLICT
+// mode is the candidate-block resolve: landmarks and points are the same
+// packed candidate set, and the output is C32[j * stride + p] = the bits r of
+// rows i = 32 p + r < j whose ball holds candidate j, plus rowflag[j] = 1 when
+// any bit is set.
+constexpr int RM_WAVES = 8;
+constexpr int RM_THREADS = RM_WAVES * 64;
+constexpr int RM_MP = 2;
 
-// One wave = MP panels of 32 landmarks x a contiguous range of 32-point tiles.
-// KS = K steps per chunk (all of K when nch == 1).
-template <int KS, int MP, bool F16>
-__global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsView P, double e2,
-                                                           const int32_t *__restrict__ A, const int64_t *blk,
-                                                           RangeOut o, int NG, int64_t tpc, int nch)
+// Tiles per LDS stage: the next stage's loads have TPS tiles of matrix work
+// to arrive in, and the workgroup synchronises once per stage.
+#ifndef BM_STAGE_TILES
+#define BM_STAGE_TILES 8
+#endif
+__host__ __device__ constexpr int stage_tiles(bool chunked, int ks)
 {
-    const int64_t ord0 = blk[0];
-    const int na = (int)blk[1];
-    const int lane = lane_id();
-    const int col = lane & 31, half = lane >> 5;
-    const int64_t wave = (int64_t)blockIdx.x * (RM_THREADS / 64) + (threadIdx.x >> 6);
-    const int g = (int)(wave % NG);
-    const int64_t c = wave / NG;
-    const int pbase = g * MP;                       // first panel of this wave
-    if (pbase * 32 >= na) return;                   // wave-uniform
-    const int64_t NT = (P.n + 31) / 32;
+    return chunked ? 1 : (ks <= 4 ? BM_STAGE_TILES : ks <= 6 ? (BM_STAGE_TILES + 1) / 2 : (BM_STAGE_TILES + 3) / 4);
+}
+// Staging vectors per thread for one stage: TPS tiles of S steps plus 96 thresholds each.
+__host__ __device__ constexpr int stage_slots(int S, int tps) { return (tps * (S * 64 + 96) + RM_THREADS - 1) / RM_THREADS; }
+
+template <int KS, bool F16, bool CONFLICT, int SLOTS, bool CHUNKED>
+__global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsView P, const int32_t *n_dev, double e2,
+                                                           const int32_t *__restrict__ A, const int64_t *blk,
+                                                           RangeOut o, uint32_t *C32, int c32_stride, int *rowflag,
+                                                           int NGW, int64_t tpc, int nch)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int S = a.S;
+    // LDS: 2 buffers of TPS tiles of [S][64] u32x4 operands, then their thresholds
+    constexpr int TPS = stage_tiles(CHUNKED, KS);
+    const int buf_words = S * 64;                                  // u32x4 per tile
+    u32x4 *sB = (u32x4 *)smem;                                     // [2][TPS][S*64]
+    float *sT = (float *)(sB + 2 * TPS * buf_words);               // [2][TPS][3][32]
+    float *sC = sT + 2 * TPS * 96;                                 // [RM_WAVES*RM_MP*32] accumulator starts
+    float *sN = sC + RM_THREADS;                                   // [RM_WAVES*RM_MP*32] norm bounds
+
+    const int64_t n = n_dev ? (int64_t)*n_dev : P.n;
+    const int64_t ord0 = CONFLICT ? 0 : blk[0];
+    const int na = CONFLICT ? (int)n : (int)blk[1];
+    const int wid = (int)(threadIdx.x >> 6), lane = lane_id(), col = lane & 31, half = lane >> 5;
+    const int g = (int)(blockIdx.x % NGW);
+    const int64_t c = blockIdx.x / NGW;
+    if (g * RM_WAVES * RM_MP * 32 >= na) return;                   // workgroup-uniform
+    const int64_t NT = (n + 31) / 32;
     const int64_t t0 = c * tpc;
     const int64_t t1 = min(NT, t0 + tpc);
-    if (t0 >= t1) return;
-    const int S = a.S;
+    if (t0 >= t1) return;                                          // workgroup-uniform
+    const int pbase = (g * RM_WAVES + wid) * RM_MP;                // first panel of this wave
+    const bool live = pbase * 32 < na;                             // wave-uniform
 
-    // landmark ranks of this lane's A-operand rows and accumulator rows
-    int32_t arank[MP];
-    f32x16 cinit[MP];
-    float aw[MP];
+    // ---- the workgroup's landmarks: one per thread into LDS (start value, norm bound)
+    static_assert(RM_WAVES * RM_MP * 32 == RM_THREADS, "one landmark per thread");
+    {
+        const int aj = g * RM_THREADS + (int)threadIdx.x;
+        float cv = 0.f, nv = 0.f;
+        if (aj < na) {
+            const int32_t r = A ? A[aj] : aj;
+            cv = a.cinit[r];
+            nv = a.nuup[r];
+        }
+        sC[threadIdx.x] = cv;
+        sN[threadIdx.x] = nv;
+    }
+    __syncthreads();
+
+    // ---- this wave's panels: ranks, accumulator starts, norm bound, A operands
+    int32_t arank[RM_MP];
+    f32x16 cinit[RM_MP];
+    float aw[RM_MP];
+    u32x4 areg[RM_MP][KS];
 #pragma unroll
-    for (int pi = 0; pi < MP; ++pi) {
+    for (int pi = 0; pi < RM_MP; ++pi) {
         const int ai = (pbase + pi) * 32 + col;
-        arank[pi] = ai < na ? A[ai] : -1;
-        float nmax = ai < na ? a.nuup[arank[pi]] : 0.f;
+        arank[pi] = ai < na ? (A ? A[ai] : ai) : -1;
+        const int lbase = (wid * RM_MP + pi) * 32;                 // this panel in sC / sN
+        float nmax = sN[lbase + col];
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) nmax = fmaxf(nmax, __shfl_xor(nmax, off, 64));
-        aw[pi] = next_up(a.alpha * nmax);
+        for (int off = 16; off > 0; off >>= 1) nmax = fmaxf(nmax, __shfl_xor(nmax, off, 64));
+        const float w = next_up(a.alpha * nmax);
+        aw[pi] = next_up(w + w * 0x1p-22f);          // see k_mfma_scalars: rounding slack
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int aj = (pbase + pi) * 32 + acc_row(i, half);
-            cinit[pi][i] = aj < na ? a.cinit[A[aj]] : 0.f;
+        for (int j = 0; j < 4; ++j) {                // rows 8j + 4 half + 0..3 of the panel
+            const float4 q = *(const float4 *)(sC + lbase + 8 * j + 4 * half);
+            cinit[pi][4 * j + 0] = q.x;
+            cinit[pi][4 * j + 1] = q.y;
+            cinit[pi][4 * j + 2] = q.z;
+            cinit[pi][4 * j + 3] = q.w;
         }
     }
-
-    u32x4 areg[MP][KS];
     auto load_a = [&](int ch) {
 #pragma unroll
-        for (int pi = 0; pi < MP; ++pi)
+        for (int pi = 0; pi < RM_MP; ++pi)
 #pragma unroll
             for (int s = 0; s < KS; ++s) {
                 const int ss = ch * KS + s;
@@ -229,53 +289,130 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
                 areg[pi][s] = v;
             }
     };
-    if (nch == 1) load_a(0);
+    if (!CHUNKED && live) load_a(0);
+
+    // ---- staging of one stage: TPS tiles x (S*64 operand vectors + 96 threshold floats)
+    const int tile_items = buf_words + 96;
+    const int items = TPS * tile_items;
+    u32x4 pre[SLOTS];
+    auto gload = [&](int64_t ts) {
+#pragma unroll
+        for (int k = 0; k < SLOTS; ++k) {
+            const int it = (int)threadIdx.x + k * RM_THREADS;
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (it < items) {
+                const int tt = it / tile_items, r = it - tt * tile_items;
+                const int64_t t = ts + tt;
+                if (t < t1) {
+                    if (r < buf_words) {
+                        v = *(const u32x4 *)(a.Pop + ((t * S) * 64 + r) * 8);
+                    } else {
+                        const int q = r - buf_words, which = q >> 5;
+                        const int64_t pt = t * 32 + (q & 31);
+                        float f = INFINITY;
+                        if (pt < n) f = which == 0 ? a.U[pt] : which == 1 ? a.V[pt] : a.Z[pt];
+                        v[0] = __float_as_uint(f);
+                    }
+                }
+            }
+            pre[k] = v;
+        }
+    };
+    // LDS per buffer: [TPS][S*64] operand vectors, then [TPS][96] thresholds
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int k = 0; k < SLOTS; ++k) {
+            const int it = (int)threadIdx.x + k * RM_THREADS;
+            if (it < items) {
+                const int tt = it / tile_items, r = it - tt * tile_items;
+                if (r < buf_words) sB[(buf * TPS + tt) * buf_words + r] = pre[k];
+                else sT[(buf * TPS + tt) * 96 + (r - buf_words)] = __uint_as_float(pre[k][0]);
+            }
+        }
+    };
 
     unsigned long long band = 0;
-    for (int64_t t = t0; t < t1; ++t) {
+    // Let the setup loads (A operands, accumulator starts) land before the loop,
+    // so the only loads in flight inside it are the next stage's staging loads
+    // and the waitcnt pass need not wait for them before the matrix ops.
+    __builtin_amdgcn_s_waitcnt(0);
+    gload(t0);
+    for (int64_t ts = t0; ts < t1; ts += TPS) {
+        const int buf = (int)(((ts - t0) / TPS) & 1);
+        lstore(buf);
+        __syncthreads();
+        if (ts + TPS < t1) gload(ts + TPS);
+        if (!live) continue;
+      for (int tt = 0; tt < TPS; ++tt) {
+        const int64_t t = ts + tt;
+        if (t >= t1) break;                                             // wave-uniform
+        const int sb = (buf * TPS + tt) * buf_words;                    // this tile's operands in LDS
+        const int stt = (buf * TPS + tt) * 96;                          // and thresholds
         const int64_t p = t * 32 + col;
-        const bool pv = p < P.n;
-        f32x16 acc[MP];
-#pragma unroll
-        for (int pi = 0; pi < MP; ++pi) acc[pi] = cinit[pi];
-        for (int ch = 0; ch < nch; ++ch) {
-            if (nch > 1) load_a(ch);
+        const bool pv = p < n;
+        const float Ux = sT[stt + col], Vx = sT[stt + 32 + col], Zx = sT[stt + 64 + col];
+        f32x16 acc[RM_MP];
+        if (!CHUNKED) {
             u32x4 breg[KS];
 #pragma unroll
-            for (int s = 0; s < KS; ++s) {
-                const int ss = ch * KS + s;
-                breg[s] = ss < S ? *(const u32x4 *)(a.Pop + (((t * S + ss) * 64) + lane) * 8)
-                                 : u32x4{0u, 0u, 0u, 0u};
-            }
+            for (int s = 0; s < KS; ++s) breg[s] = sB[sb + s * 64 + lane];
 #pragma unroll
             for (int s = 0; s < KS; ++s)
 #pragma unroll
-                for (int pi = 0; pi < MP; ++pi) acc[pi] = mfma32<F16>(areg[pi][s], breg[s], acc[pi]);
+                for (int pi = 0; pi < RM_MP; ++pi)
+                    acc[pi] = mfma32<F16>(areg[pi][s], breg[s], s == 0 ? cinit[pi] : acc[pi]);
+        } else {
+#pragma unroll
+            for (int pi = 0; pi < RM_MP; ++pi) acc[pi] = cinit[pi];
+            for (int ch = 0; ch < nch; ++ch) {
+                load_a(ch);
+                u32x4 breg[KS];
+#pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                    const int ss = ch * KS + s;
+                    breg[s] = ss < S ? sB[sb + ss * 64 + lane] : u32x4{0u, 0u, 0u, 0u};
+                }
+#pragma unroll
+                for (int s = 0; s < KS; ++s)
+#pragma unroll
+                    for (int pi = 0; pi < RM_MP; ++pi) acc[pi] = mfma32<F16>(areg[pi][s], breg[s], acc[pi]);
+            }
         }
 
         bool cov = false;
-        const float Ux = pv ? a.U[p] : INFINITY;
-        const float Vx = pv ? a.V[p] : INFINITY;
-        const float Zx = pv ? a.Z[p] : INFINITY;
-        const int64_t xo = pv ? orig_index(P, p) : 0;
 #pragma unroll
-        for (int pi = 0; pi < MP; ++pi) {
+        for (int pi = 0; pi < RM_MP; ++pi) {
             const int abase = (pbase + pi) * 32;
             if (abase >= na) break;                                      // wave-uniform
+            const f32x16 av = acc[pi];
+            // u, v: conservative thresholds for this point and panel (U, V and aw carry
+            // the slack for these two roundings); +inf for padding points
+            const float u = Ux - aw[pi];
+            if (!CONFLICT) {
+                // fast path: is any pair of the 32x32 tile possibly a member?
+                const float cut = a.refine ? u : Zx;
+                float m = fmaxf(fmaxf(av[0], av[1]), av[2]);
+                m = fmaxf(fmaxf(m, av[3]), av[4]);
+                m = fmaxf(fmaxf(m, av[5]), av[6]);
+                m = fmaxf(fmaxf(m, av[7]), av[8]);
+                m = fmaxf(fmaxf(m, av[9]), av[10]);
+                m = fmaxf(fmaxf(m, av[11]), av[12]);
+                m = fmaxf(fmaxf(m, av[13]), av[14]);
+                m = fmaxf(m, av[15]);
+                if (!__ballot(!(m <= cut))) continue;
+            }
             uint32_t mem = 0;
+            const int64_t xo = pv ? orig_index(P, p) : 0;
             if (a.refine) {
-                const float u = pv ? next_down(Ux - aw[pi]) : INFINITY;
-                uint64_t any = 0;
-#pragma unroll
-                for (int i = 0; i < 16; ++i) any |= __ballot(!(acc[pi][i] <= u));
-                if (!any) continue;                                      // every pair of the tile is out
-                const float v = pv ? next_up(Vx + aw[pi]) : INFINITY;
+                const float v = Vx + aw[pi];
                 uint32_t bnd = 0;
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
-                    const float gval = acc[pi][i];
-                    const bool live = pv && (abase + acc_row(i, half) < na) && !(gval <= u);
-                    if (live) {
+                    const float gval = av[i];
+                    const int ai = abase + acc_row(i, half);
+                    bool ok = pv && ai < na && !(gval <= u);
+                    if (CONFLICT) ok = ok && ai < p;
+                    if (ok) {
                         if (gval > v) mem |= 1u << i;
                         else bnd |= 1u << i;
                     }
@@ -284,18 +421,32 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
                     const int i = __builtin_ctz(bnd);
                     bnd &= bnd - 1;
                     ++band;
-                    const int32_t lr = A[abase + acc_row(i, half)];
+                    const int ai = abase + acc_row(i, half);
+                    const int32_t lr = A ? A[ai] : ai;
                     if (exact_member(P, orig_index(P, lr), xo, e2)) mem |= 1u << i;
                 }
             } else {
 #pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int ai = abase + acc_row(i, half);
+                    if (pv && ai < na && (!CONFLICT || ai < p) && av[i] > Zx) mem |= 1u << i;
+                }
+            }
+            if (CONFLICT) {
+                uint32_t w = 0;
+#pragma unroll
                 for (int i = 0; i < 16; ++i)
-                    if (pv && abase + acc_row(i, half) < na && acc[pi][i] > Zx) mem |= 1u << i;
+                    if ((mem >> i) & 1u) w |= 1u << acc_row(i, half);
+                w |= __shfl_xor(w, 32, 64);
+                if (half == 0 && pv) {
+                    C32[p * c32_stride + (pbase + pi)] = w;
+                    if (w) rowflag[p] = 1;
+                }
+                continue;
             }
             // append this lane's members with one atomic per wave
             const int cnt = __popc(mem);
-            const uint64_t any_mem = __ballot(cnt != 0);
-            if (!any_mem) continue;
+            if (!__ballot(cnt != 0)) continue;
             const int incl = wave_incl_scan(cnt);
             const int total = __shfl(incl, 63, 64);
             unsigned long long base = 0;
@@ -310,15 +461,16 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
                 ++base;
             }
         }
-        if (o.covered) {
+        if (!CONFLICT && o.covered) {
             const uint64_t m = __ballot(cov);
             const uint64_t bits = (m | (m >> 32)) & 0xffffffffull;
             if (bits && lane == 0)
                 atomicOr((unsigned long long *)&o.covered[(t * 32) >> 6], (unsigned long long)(bits << ((t * 32) & 63)));
         }
+      }
     }
     band = wave_sum(band);
-    if (band && lane == 0) atomicAdd(&o.st->band, band);
+    if (band && lane == 0 && o.st) atomicAdd(&o.st->band, band);
 }
 
 // ---- self-check of the matrix-core behaviour the error bound relies on -------------------
@@ -379,50 +531,126 @@ hipError_t run_selfcheck(int *flags_dev, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int KS, int MP, bool F16>
-static hipError_t launch_ks(const MfmaArgs &a, const PointsView &P, double e2, const int32_t *A, const int64_t *blk,
-                            int na_max, const RangeOut &o, int nch, hipStream_t s)
+template <int KS, bool F16, bool CONFLICT, int SLOTS, bool CHUNKED>
+static hipError_t launch_ks(const MfmaArgs &a, const PointsView &P, const int32_t *n_dev, double e2, const int32_t *A,
+                            const int64_t *blk, int na_max, int64_t n_max, const RangeOut &o, uint32_t *C32,
+                            int c32_stride, int *rowflag, int nch, hipStream_t s)
 {
     const int npan = (na_max + 31) / 32;
-    const int NG = (npan + MP - 1) / MP;
-    const int64_t NT = (P.n + 31) / 32;
-    // aim for about 8 waves per SIMD over the chip: 256 CUs x 4 SIMDs x 8
-    const int64_t target_waves = 8192;
-    int64_t chunks = (target_waves + NG - 1) / NG;
+    const int per_wg = RM_WAVES * RM_MP;
+    const int NGW = (npan + per_wg - 1) / per_wg;
+    const int64_t NT = (n_max + 31) / 32;
+    // about one workgroup per CU (256 CUs) unless BM_RANGE_WORKGROUPS says otherwise
+    static const int64_t env_wg = [] {
+        const char *e = getenv("BM_RANGE_WORKGROUPS");
+        return e ? atoll(e) : 0LL;
+    }();
+    const int64_t target_wg = env_wg > 0 ? env_wg : 256;
+    int64_t chunks = (target_wg + NGW - 1) / NGW;
     if (chunks > NT) chunks = NT;
     if (chunks < 1) chunks = 1;
     const int64_t tpc = (NT + chunks - 1) / chunks;
     chunks = (NT + tpc - 1) / tpc;
-    const int64_t waves = (int64_t)NG * chunks;
-    const int64_t blocks = (waves + 3) / 4;
-    k_range_mfma<KS, MP, F16><<<(unsigned)blocks, RM_THREADS, 0, s>>>(a, P, e2, A, blk, o, NG, tpc, nch);
+    const int64_t wgs = (int64_t)NGW * chunks;
+    constexpr int TPS = stage_tiles(CHUNKED, KS);
+    const size_t shmem = (size_t)2 * TPS * (a.S * 64 * 16 + 96 * sizeof(float)) + 2 * RM_THREADS * sizeof(float);
+    k_range_mfma<KS, F16, CONFLICT, SLOTS, CHUNKED><<<(unsigned)wgs, RM_THREADS, shmem, s>>>(a, P, n_dev, e2, A, blk, o, C32, c32_stride,
+                                                                          rowflag, NGW, tpc, nch);
     return hipGetLastError();
 }
 
-template <bool F16>
-static hipError_t dispatch(const MfmaArgs &a, const PointsView &P, double e2, const int32_t *A, const int64_t *blk,
-                           int na_max, const RangeOut &o, hipStream_t s)
+template <bool F16, bool CONFLICT>
+static hipError_t dispatch(const MfmaArgs &a, const PointsView &P, const int32_t *n_dev, double e2, const int32_t *A,
+                           const int64_t *blk, int na_max, int64_t n_max, const RangeOut &o, uint32_t *C32,
+                           int c32_stride, int *rowflag, hipStream_t s)
 {
-    const int S = a.S;
-    switch (S) {
-    case 1: return launch_ks<1, 2, F16>(a, P, e2, A, blk, na_max, o, 1, s);
-    case 2: return launch_ks<2, 2, F16>(a, P, e2, A, blk, na_max, o, 1, s);
-    case 3: return launch_ks<3, 2, F16>(a, P, e2, A, blk, na_max, o, 1, s);
-    case 4: return launch_ks<4, 2, F16>(a, P, e2, A, blk, na_max, o, 1, s);
-    case 5: return launch_ks<5, 2, F16>(a, P, e2, A, blk, na_max, o, 1, s);
-    case 6: return launch_ks<6, 2, F16>(a, P, e2, A, blk, na_max, o, 1, s);
-    case 7: return launch_ks<7, 2, F16>(a, P, e2, A, blk, na_max, o, 1, s);
-    case 8: return launch_ks<8, 2, F16>(a, P, e2, A, blk, na_max, o, 1, s);
-    default: return launch_ks<8, 2, F16>(a, P, e2, A, blk, na_max, o, (S + 7) / 8, s);
+#define BM_KS(k, nch, slots) \
+    launch_ks<k, F16, CONFLICT, slots, (nch > 1)>(a, P, n_dev, e2, A, blk, na_max, n_max, o, C32, c32_stride, rowflag, nch, s)
+    switch (a.S) {
+    case 1: return BM_KS(1, 1, stage_slots(1, stage_tiles(false, 1)));
+    case 2: return BM_KS(2, 1, stage_slots(2, stage_tiles(false, 2)));
+    case 3: return BM_KS(3, 1, stage_slots(3, stage_tiles(false, 3)));
+    case 4: return BM_KS(4, 1, stage_slots(4, stage_tiles(false, 4)));
+    case 5: return BM_KS(5, 1, stage_slots(5, stage_tiles(false, 5)));
+    case 6: return BM_KS(6, 1, stage_slots(6, stage_tiles(false, 6)));
+    case 7: return BM_KS(7, 1, stage_slots(7, stage_tiles(false, 7)));
+    case 8: return BM_KS(8, 1, stage_slots(8, stage_tiles(false, 8)));
+    default: return launch_ks<8, F16, CONFLICT, stage_slots(kMaxMfmaSteps, stage_tiles(true, 8)), true>(
+                 a, P, n_dev, e2, A, blk, na_max, n_max, o, C32, c32_stride, rowflag, (a.S + 7) / 8, s);
     }
+#undef BM_KS
 }
 
 hipError_t launch_range_mfma(const MfmaArgs &a, const PointsView &P, double e2, const int32_t *A,
                              const int64_t *blk, int na_max, const RangeOut &o, hipStream_t s)
 {
+    if (a.S > kMaxMfmaSteps) return hipErrorInvalidValue;
     if (P.n <= 0 || na_max <= 0) return hipSuccess;
-    if (a.kind == MFMA_F16) return dispatch<true>(a, P, e2, A, blk, na_max, o, s);
-    return dispatch<false>(a, P, e2, A, blk, na_max, o, s);
+    if (a.kind == MFMA_F16) return dispatch<true, false>(a, P, nullptr, e2, A, blk, na_max, P.n, o, nullptr, 0, nullptr, s);
+    return dispatch<false, false>(a, P, nullptr, e2, A, blk, na_max, P.n, o, nullptr, 0, nullptr, s);
+}
+
+hipError_t launch_resolve_mfma(const MfmaArgs &packed, const PointsView &Pc, const int32_t *nc_dev, double e2, int B,
+                               uint32_t *C32, int *rowflag, GreedyState *st, hipStream_t s)
+{
+    if (packed.S > kMaxMfmaSteps) return hipErrorInvalidValue;
+    RangeOut o{nullptr, nullptr, 0, st, 0};
+    const int stride = 2 * ((B + 63) / 64);
+    if (packed.kind == MFMA_F16)
+        return dispatch<true, true>(packed, Pc, nc_dev, e2, nullptr, nullptr, B, B, o, C32, stride, rowflag, s);
+    return dispatch<false, true>(packed, Pc, nc_dev, e2, nullptr, nullptr, B, B, o, C32, stride, rowflag, s);
+}
+
+// Copy the gathered candidates' operands and scalars into a packed set
+// (candidate j in place of rank j) for the resolve, and their original indices.
+__global__ void k_pack_candidates(MfmaArgs a, const int32_t *cand, const GreedyState *st, const int32_t *perm, int B,
+                                  MfmaArgs out, int32_t *cand_orig)
+{
+    const int nc = st->nc;
+    const int S = a.S;
+    const int64_t Bp = ((B + 31) / 32) * 32;
+    const int64_t nvec = Bp * S * 2;                 // (candidate, step, half) 16-byte vectors
+    const bool two = a.Qop != a.Pop;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < nvec + Bp;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        if (g < nvec) {
+            const int half = (int)(g & 1);
+            const int64_t js = g >> 1;
+            const int st_ = (int)(js % S);
+            const int64_t j = js / S;
+            const int64_t dst = ((((j >> 5) * S + st_) * 64) + (j & 31) + 32 * half) * 8;
+            u32x4 vp = {0u, 0u, 0u, 0u}, vq = {0u, 0u, 0u, 0u};
+            if (j < nc) {
+                const int64_t r = cand[j];
+                const int64_t src = ((((r >> 5) * S + st_) * 64) + (r & 31) + 32 * half) * 8;
+                vp = *(const u32x4 *)(a.Pop + src);
+                if (two) vq = *(const u32x4 *)(a.Qop + src);
+            }
+            *(u32x4 *)((uint16_t *)out.Pop + dst) = vp;
+            if (two) *(u32x4 *)((uint16_t *)out.Qop + dst) = vq;
+        } else {
+            const int64_t j = g - nvec;
+            const bool v = j < nc;
+            const int32_t r = v ? cand[j] : 0;
+            ((float *)out.cinit)[j] = v ? a.cinit[r] : 0.f;
+            ((float *)out.nuup)[j] = v ? a.nuup[r] : 0.f;
+            ((float *)out.U)[j] = v ? a.U[r] : INFINITY;
+            ((float *)out.V)[j] = v ? a.V[r] : INFINITY;
+            ((float *)out.Z)[j] = v ? a.Z[r] : INFINITY;
+            cand_orig[j] = v ? (perm ? perm[r] : r) : 0;
+        }
+    }
+}
+
+hipError_t launch_pack_candidates(const MfmaArgs &a, const int32_t *cand, const GreedyState *st, const int32_t *perm,
+                                  int B, const MfmaArgs &out, int32_t *cand_orig, hipStream_t s)
+{
+    const int64_t Bp = ((B + 31) / 32) * 32;
+    const int64_t total = Bp * a.S * 2 + Bp;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    k_pack_candidates<<<(int)blocks, 256, 0, s>>>(a, cand, st, perm, B, out, cand_orig);
+    return hipGetLastError();
 }
 
 } // namespace bm
