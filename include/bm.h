@@ -71,11 +71,14 @@ typedef enum {           /* stored dtype of the points (row-major n x d)        
 } bm_dtype;
 
 typedef enum {           /* arithmetic of the range pass filter                              */
-    BM_PATH_AUTO = 0,    /* F16 for float16 storage, else BF16 or BF16X3 from the norm/eps ratio */
+    BM_PATH_AUTO = 0,    /* F16 for float16 storage; else F16 (scaled) or BF16X3 from the band
+                            each would have at the data's largest norm; FP32 past d = 480     */
     BM_PATH_FP32 = 1,    /* FP32 direct difference on the vector ALUs (the plain baseline)   */
     BM_PATH_BF16 = 2,    /* one BF16 product per coordinate on MFMA, FP32 accumulation       */
     BM_PATH_BF16X3 = 3,  /* hi/lo BF16 split, three products per coordinate on MFMA          */
-    BM_PATH_F16 = 4      /* FP16 operands on MFMA (exact for float16 storage)                */
+    BM_PATH_F16 = 4      /* FP16 operands on MFMA: the stored values for float16 storage
+                            (exact); float32/float64 data scaled by a power of two into
+                            float16 range and rounded to nearest                          */
 } bm_path;
 
 typedef struct {
@@ -183,7 +186,9 @@ int bm_range_sets(const void *points, int64_t n, int32_t d, int32_t dtype, doubl
  * Sec. 5.2), abs_err its absolute part.  delta is the additive radius error of
  * Sec. 5.1 for points of squared norm <= max_sq_norm:
  *     delta = max(eps - sqrt(eps^2 - w), sqrt(eps^2 + w) - eps),
- * w the bound on |estimated D - D| at D = eps^2.
+ * w the bound on |estimated D - D| at D = eps^2, including the FP32 rounding
+ * of the unrefined threshold: with refine = 0 every lost or spurious
+ * membership has its true distance in [eps - delta, eps + delta).
  * Inputs: path (not AUTO), dtype and d of the stored points, eps, the largest
  * squared norm and the largest |coordinate| of the data.  No device needed.
  */

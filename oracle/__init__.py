@@ -77,6 +77,8 @@ def configure(lib):
     lib.bmo_free.argtypes = [P(_Result)]
     lib.bmo_free.restype = None
     lib.bmo_threads.restype = ctypes.c_int
+    lib.bmo_first_member.argtypes = [vp, i64, i32, i32, f64, P(i32), i64, P(i32), i64, P(i64)]
+    lib.bmo_first_member.restype = ctypes.c_int
     return lib
 
 
@@ -202,6 +204,19 @@ def knn_eps(points, k: int):
     if rc != 0:
         raise ValueError(f"bmo_knn_eps failed with code {rc}")
     return eps.value, kd
+
+
+def first_member(points, landmarks, eps: float, queries) -> np.ndarray:
+    """Position (selection order) of the first landmark whose ball holds each query, or -1."""
+    x = _points(points)
+    lm = np.ascontiguousarray(landmarks, dtype=np.int32)
+    q = np.ascontiguousarray(queries, dtype=np.int32)
+    out = np.empty(q.shape[0], np.int64)
+    rc = _load().bmo_first_member(x.ctypes.data, x.shape[0], x.shape[1], DTYPE_CODE[x.dtype], float(eps),
+                                  _i32p(lm), lm.shape[0], _i32p(q), q.shape[0], _i64p(out))
+    if rc != 0:
+        raise ValueError(f"bmo_first_member failed with code {rc}")
+    return out
 
 
 def covering_radius(points, landmarks) -> float:

@@ -468,6 +468,26 @@ double bmo_separation(const void *pts, int64_t n, int32_t d, int32_t dtype,
     return sqrt(best);
 }
 
+int bmo_first_member(const void *pts, int64_t n, int32_t d, int32_t dtype, double eps,
+                     const int32_t *landmarks, int64_t L, const int32_t *queries, int64_t nq,
+                     int64_t *first)
+{
+    if (check_args(pts, n, d, dtype, eps) || L < 0 || nq < 0) return -1;
+    const double e2 = eps * eps;
+    double *w = widen(pts, n, d, dtype);
+    if (!w) return -2;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < nq; ++q) {
+        int64_t f = -1;
+        const double *xq = w + (int64_t)queries[q] * d;
+        for (int64_t i = 0; i < L && f < 0; ++i)
+            if (sqdist_w(w + (int64_t)landmarks[i] * d, xq, d, e2) < e2) f = i;
+        first[q] = f;
+    }
+    free(w);
+    return 0;
+}
+
 int bmo_threads(void)
 {
 #ifdef _OPENMP

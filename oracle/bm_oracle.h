@@ -74,6 +74,12 @@ double bmo_covering_radius(const void *pts, int64_t n, int32_t d, int32_t dtype,
 double bmo_separation(const void *pts, int64_t n, int32_t d, int32_t dtype,
                       const int32_t *landmarks, int64_t n_landmarks);
 
+/* For each query point, the position in `landmarks` of the first landmark
+ * whose ball holds it (-1 if none): the cover condition of the greedy. */
+int bmo_first_member(const void *pts, int64_t n, int32_t d, int32_t dtype, double eps,
+                     const int32_t *landmarks, int64_t n_landmarks, const int32_t *queries,
+                     int64_t n_queries, int64_t *first);
+
 /* OpenMP threads the oracle runs with. */
 int bmo_threads(void);
 

@@ -151,7 +151,6 @@ void check_common(const void *points, int64_t n, int32_t d, int32_t dtype, doubl
     if (o.refine != 0 && o.refine != 1) fail(BM_EINVAL, "refine must be 0 or 1");
     if (o.block < 0 || o.block > 4096) fail(BM_EINVAL, "block must be 0 (automatic) or 1..4096");
     if (o.max_device_bytes < 0 || o.init_member_capacity < 0) fail(BM_EINVAL, "negative size option");
-    if (o.path == BM_PATH_F16 && dtype != BM_F16) fail(BM_EINVAL, "path F16 needs float16 storage");
     if ((o.profile != 0 && o.profile != 1) || o.reserved != 0) fail(BM_EINVAL, "bad profile/reserved option");
 }
 
@@ -245,17 +244,28 @@ int auto_block(int64_t n, int path)
     return 64;
 }
 
-// BF16 with one product unless its band would be wide against eps^2, then the
-// three-product split; float16 storage is exact in f16.
+// Path choice from the band each path would have at the largest norm, relative
+// to eps^2: float16 storage -> F16 (exact operands); otherwise F16 on scaled
+// data when its band is under 2% of eps^2 (same matrix-core cost as BF16 with
+// an 8x narrower band), else the three-product BF16 split; FP32 when d is past
+// the matrix-core kernel's K.
+double band_fraction(int kind, int dtype, int d, double e2, double max_nu, double max_abs)
+{
+    const int K = ((kind == MFMA_BF16X3 ? 3 * d : d) + 15) / 16 * 16;
+    const double s = (kind == MFMA_F16) ? f16_scale(dtype, max_abs) : 1.0;
+    const MfmaBound b = mfma_bound(kind, d, K, e2 * s * s, std::sqrt(max_nu) * s, max_abs * s, true, dtype == BM_F16);
+    const double half_width = 2.0 * ((b.alpha + b.beta) * max_nu * s * s + b.abs_err);
+    return half_width / (e2 * s * s);
+}
+
 int auto_path(int dtype, int d, double e2, double max_nu, double max_abs)
 {
-    if (dtype == BM_F16 && (d + 15) / 16 <= kMaxMfmaSteps) return BM_PATH_F16;
-    const int K1 = (d + 15) / 16 * 16;
-    if (K1 / 16 > kMaxMfmaSteps) return BM_PATH_FP32;            // beyond the MFMA kernel's K
-    if ((3 * d + 15) / 16 > kMaxMfmaSteps) return BM_PATH_BF16;
-    const MfmaBound b1 = mfma_bound(MFMA_BF16, d, K1, e2, std::sqrt(max_nu), max_abs, false);
-    const double half_width = 2.0 * ((b1.alpha + b1.beta) * max_nu + b1.abs_err);   // in D units
-    return half_width <= 0.02 * e2 ? BM_PATH_BF16 : BM_PATH_BF16X3;
+    const int S1 = (d + 15) / 16, S3 = (3 * d + 15) / 16;
+    if (S1 > kMaxMfmaSteps) return BM_PATH_FP32;
+    if (dtype == BM_F16) return BM_PATH_F16;
+    if (band_fraction(MFMA_F16, dtype, d, e2, max_nu, max_abs) <= 0.02) return BM_PATH_F16;
+    if (S3 <= kMaxMfmaSteps) return BM_PATH_BF16X3;
+    return BM_PATH_F16;
 }
 
 bm_result *run_job(const Job &job, const bm_options &o)
@@ -331,12 +341,17 @@ bm_result *run_job(const Job &job, const bm_options &o)
             const size_t words = mfma_operand_words(n, S);
             uint16_t *Pop = dev.alloc<uint16_t>(words);
             uint16_t *Qop = (kind == MFMA_BF16X3) ? dev.alloc<uint16_t>(words) : Pop;
-            hip_ok(launch_mfma_operands(P, kind, S, Pop, Qop, dev.s), "mfma_operands");
+            // F16 on float32/float64 storage works in units scaled by a power of two
+            const double scale = (kind == MFMA_F16) ? f16_scale(job.dtype, max_abs) : 1.0;
+            hip_ok(launch_mfma_operands(P, kind, S, scale, Pop, Qop, dev.s), "mfma_operands");
             const int flags = device_flags(dev.dev, dev.s);
             if ((flags & 3) != 3) fail(BM_EINTERNAL, "matrix-core layout self-check failed on this device");
-            const MfmaBound mb = mfma_bound(kind, d, 16 * S, e2, std::sqrt(max_nu), max_abs, (flags & 4) != 0);
+            const double sc2 = scale * scale;
+            const MfmaBound mb = mfma_bound(kind, d, 16 * S, e2 * sc2, std::sqrt(max_nu) * scale, max_abs * scale,
+                                            (flags & 4) != 0, job.dtype == BM_F16);
             float *sc = dev.alloc<float>((size_t)n * 5);
-            hip_ok(launch_mfma_scalars(n, nu, mb, e2, d, sc, sc + n, sc + 2 * n, sc + 3 * n, sc + 4 * n, dev.s),
+            hip_ok(launch_mfma_scalars(n, nu, sc2, mb, e2 * sc2, d, sc, sc + n, sc + 2 * n, sc + 3 * n, sc + 4 * n,
+                                       dev.s),
                    "mfma_scalars");
             ma.Pop = Pop;
             ma.Qop = Qop;
@@ -787,19 +802,23 @@ int bm_error_bound(int32_t path, int32_t dtype, int32_t d, double eps, double ma
             // |s32 - D| <= g32 (sqrt(D) + E)^2 + 2 E sqrt(D) + E^2 + abs at D = e2
             const double se = std::sqrt(e2);
             w = g32 * (se + E) * (se + E) + 2.0 * E * se + E * E + out->abs_err;
+            w += std::ldexp(e2, -23);                                   // RN32 of the unrefined threshold
             out->exact_range = e2 >= std::ldexp(1.0, -100) && e2 <= std::ldexp(1.0, 100) && max_abs <= std::ldexp(1.0, 60);
         } else if (path == BM_PATH_BF16 || path == BM_PATH_BF16X3 || path == BM_PATH_F16) {
-            if (path == BM_PATH_F16 && dtype != BM_F16) fail(BM_EINVAL, "path F16 needs float16 storage");
             const int Kraw = (path == BM_PATH_BF16X3) ? 3 * d : d;
             const int K = (Kraw + 15) / 16 * 16;
-            const MfmaBound b = mfma_bound(path, d, K, e2, std::sqrt(max_sq_norm), max_abs, kF16SubnormalsOk);
+            // F16 on wider storage works on data scaled by s (a power of two); report in data units
+            const double s = (path == BM_PATH_F16) ? f16_scale(dtype, max_abs) : 1.0;
+            const MfmaBound b = mfma_bound(path, d, K, e2 * s * s, std::sqrt(max_sq_norm) * s, max_abs * s,
+                                           kF16SubnormalsOk, dtype == BM_F16);
             out->alpha = b.alpha;
             out->beta = b.beta;
-            out->abs_err = b.abs_err;
-            out->t_in = b.t_in;
-            out->t_out = b.t_out;
+            out->abs_err = b.abs_err / (s * s);
+            out->t_in = b.t_in / (s * s);
+            out->t_out = b.t_out / (s * s);
             out->exact_range = b.sane;
-            w = 2.0 * ((b.alpha + b.beta) * max_sq_norm + b.abs_err);   // |D_est - D| = 2 |G - h|
+            w = 2.0 * ((b.alpha + b.beta) * max_sq_norm + out->abs_err);   // |D_est - D| = 2 |G - h|
+            w += std::ldexp(max_sq_norm + e2, -23);                     // RN32 of the unrefined threshold Z
         } else {
             fail(BM_EINVAL, "path must be FP32, BF16, BF16X3 or F16");
         }

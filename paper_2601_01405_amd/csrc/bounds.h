@@ -103,10 +103,27 @@ inline Fp32Thresholds fp32_thresholds(double e2, int d, int dtype, double max_no
 //                 relative, after at most 2^-24 from a float64 -> float32 step
 //           BF16X3  3 * 2^-16 (1 + 2^-6)   (hi off by 2^-8, lo by 2^-8 of the
 //                 remainder: the dropped lo.lo and residual terms)
-//           F16   0  (float16 storage is exact in f16)
-//   tau:    2^-126 for bf16 (values flushed below the normal range),
-//           2^-14 for f16 unless the device honours f16 subnormals in MFMA.
-inline MfmaBound mfma_bound(int kind, int d, int K, double e2, double max_norm, double max_abs, bool f16_subnormals_ok)
+//           F16   0 for float16 storage (exact); otherwise the data are scaled by
+//                 a power of two into float16 range and rounded: 2 rho + rho^2 with
+//                 rho = (2^-11 + 2^-24)(1 + 2^-20), in the scaled units
+//   tau:    2^-126 for bf16 (values flushed below the normal range), for f16
+//           0 (stored) or 2^-25 (rounded) when the device honours f16 subnormals
+//           in MFMA, else 2^-14.
+// Power-of-two scale that brings float32/float64 data into float16 range for
+// the F16 path: max |s x| <= 2^15 < 65504.  float16 storage is used as is (s = 1).
+inline double f16_scale(int dtype, double max_abs)
+{
+    if (dtype == 2 || !(max_abs > 0.0)) return 1.0;
+    int e;
+    std::frexp(max_abs, &e);                 // max_abs < 2^e
+    return std::ldexp(1.0, 15 - e);
+}
+
+// All inputs in the path's working units (for a scaled F16 path: e2, max_norm
+// and max_abs already multiplied by s^2, s, s).  `stored_f16` tells whether the
+// operands are the stored float16 values (exact) or roundings of wider data.
+inline MfmaBound mfma_bound(int kind, int d, int K, double e2, double max_norm, double max_abs, bool f16_subnormals_ok,
+                            bool stored_f16 = true)
 {
     MfmaBound b{};
     const double u24 = std::ldexp(1.0, -24);
@@ -123,10 +140,17 @@ inline MfmaBound mfma_bound(int kind, int d, int K, double e2, double max_norm, 
         rho_p = 3.0 * std::ldexp(1.0, -16) * (1.0 + std::ldexp(1.0, -6));
         tau = std::ldexp(1.0, -126);
         m = 3;
-    } else {
+    } else if (stored_f16) {
         rho = 0.0;
         rho_p = 0.0;
         tau = f16_subnormals_ok ? 0.0 : std::ldexp(1.0, -14);
+    } else {
+        // round to nearest float16 (11 significant bits) after at most one float32 rounding;
+        // below the normal range the error is absolute: half the subnormal spacing 2^-24,
+        // or the whole value if subnormals were flushed
+        rho = (std::ldexp(1.0, -11) + u24) * (1.0 + std::ldexp(1.0, -20));
+        rho_p = 2.0 * rho + rho * rho;
+        tau = f16_subnormals_ok ? std::ldexp(1.0, -25) : std::ldexp(1.0, -14);
     }
     const double mag = (1.0 + rho) * (1.0 + rho) * (1.0 + std::ldexp(1.0, -6));   // sum|P Q| <= mag (nu_a+nu_x)/2
     const double op_abs = 2.0 * m * tau * (1.0 + rho) * std::sqrt((double)d) * max_norm + m * (double)d * tau * tau;

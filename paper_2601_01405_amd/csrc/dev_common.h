@@ -23,9 +23,18 @@ __device__ __forceinline__ int64_t orig_index(const PointsView &P, int64_t rank)
 
 // ---- the FP64 predicate --------------------------------------------------------------
 // s(a,b) = sum over k of RN(RN(a_k - b_k)^2), added left to right with round to
-// nearest and no fused multiply-add; member iff s < e2 = RN(eps^2).  Once the
-// partial sum reaches e2 the loop stops: every term is >= 0 and rounded addition
-// is monotone, so the full sum would not be below e2 either.
+// nearest and no fused multiply-add; member iff s < e2 = RN(eps^2).  The two
+// rows are read in chunks of 8 coordinates (independent loads in flight) and
+// the terms are then added strictly in order k = 0, 1, ..., d-1.  (No early
+// exit: pairs reach this recheck only near the threshold, and the decision
+// does not depend on it.)
+template <int DT>
+__device__ __forceinline__ void load8(const void *X, int64_t off, int valid, double *v)
+{
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = e < valid ? load_coord<DT>(X, off + e) : 0.0;
+}
+
 template <int DT>
 __device__ __forceinline__ bool exact_member_t(const void *X, int32_t d, int64_t a, int64_t b,
                                                          double e2)
@@ -33,11 +42,19 @@ __device__ __forceinline__ bool exact_member_t(const void *X, int32_t d, int64_t
 #pragma clang fp contract(off)
     const int64_t oa = a * (int64_t)d, ob = b * (int64_t)d;
     double acc = 0.0;
-    for (int32_t k = 0; k < d; ++k) {
-        double t = load_coord<DT>(X, oa + k) - load_coord<DT>(X, ob + k);
-        double sq = t * t;
-        acc = acc + sq;
-        if (acc >= e2) return false;
+    for (int32_t k0 = 0; k0 < d; k0 += 8) {
+        const int valid = min(8, d - k0);
+        double va[8], vb[8];
+        load8<DT>(X, oa + k0, valid, va);
+        load8<DT>(X, ob + k0, valid, vb);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            if (e < valid) {
+                const double t = va[e] - vb[e];
+                const double sq = t * t;
+                acc = acc + sq;
+            }
+        }
     }
     return acc < e2;
 }

@@ -20,10 +20,13 @@ hipError_t launch_point_stats(const PointsView &P, double *nu, unsigned long lon
 hipError_t launch_to_f32(const PointsView &P, float *xf, hipStream_t s);
 
 // MFMA operands in the swizzled tile layout (range_mfma.hip).  Qop may equal Pop.
-hipError_t launch_mfma_operands(const PointsView &P, int kind, int S, uint16_t *Pop, uint16_t *Qop, hipStream_t s);
-// Per-point accumulator start, rounded-up norm and decision thresholds for one eps.
-hipError_t launch_mfma_scalars(int64_t n, const double *nu, const MfmaBound &b, double e2, int d, float *cinit,
-                               float *nuup, float *U, float *V, float *Z, hipStream_t s);
+// `scale` multiplies the coordinates before rounding (F16 path on wider storage; 1 otherwise).
+hipError_t launch_mfma_operands(const PointsView &P, int kind, int S, double scale, uint16_t *Pop, uint16_t *Qop,
+                                hipStream_t s);
+// Per-point accumulator start, rounded-up norm and decision thresholds for one eps,
+// in working units: nu_scale = scale^2, b and e2 already in those units.
+hipError_t launch_mfma_scalars(int64_t n, const double *nu, double nu_scale, const MfmaBound &b, double e2, int d,
+                               float *cinit, float *nuup, float *U, float *V, float *Z, hipStream_t s);
 
 // ---- greedy (greedy.hip) ----------------------------------------------------------------
 // Lists up to B uncovered ranks after the cursor and clears rowflag[0..B).

@@ -40,7 +40,7 @@ __device__ __forceinline__ uint16_t bf16_rne(float f)
 __device__ __forceinline__ double bf16_to_double(uint16_t h) { return (double)__uint_as_float((uint32_t)h << 16); }
 
 template <int DT>
-__global__ void k_mfma_operands(PointsView P, int kind, int S, uint16_t *Pop, uint16_t *Qop)
+__global__ void k_mfma_operands(PointsView P, int kind, int S, double scale, uint16_t *Pop, uint16_t *Qop)
 {
     const int64_t NT = (P.n + 31) / 32;
     const int64_t total = NT * S * 64;
@@ -61,7 +61,14 @@ __global__ void k_mfma_operands(PointsView P, int kind, int S, uint16_t *Pop, ui
             uint16_t a = 0, b = 0;
             if (p < P.n) {
                 if (kind == MFMA_F16) {
-                    if (k < d) a = b = ((const uint16_t *)P.X)[row + k];
+                    if (k < d) {
+                        if constexpr (DT == 2) {
+                            a = b = ((const uint16_t *)P.X)[row + k];          // stored float16: exact
+                        } else {                                              // exact power-of-two scale,
+                            const float v = (float)(load_coord<DT>(P.X, row + k) * scale);   // then RN to f16
+                            a = b = __builtin_bit_cast(uint16_t, (_Float16)v);
+                        }
+                    }
                 } else if (kind == MFMA_BF16) {
                     if (k < d) a = b = bf16_rne((float)load_coord<DT>(P.X, row + k));
                 } else {   // three-product split: P = [hi|hi|lo], Q = [hi|lo|hi]
@@ -90,15 +97,16 @@ __global__ void k_mfma_operands(PointsView P, int kind, int S, uint16_t *Pop, ui
     }
 }
 
-hipError_t launch_mfma_operands(const PointsView &P, int kind, int S, uint16_t *Pop, uint16_t *Qop, hipStream_t s)
+hipError_t launch_mfma_operands(const PointsView &P, int kind, int S, double scale, uint16_t *Pop, uint16_t *Qop,
+                                hipStream_t s)
 {
     const int64_t total = ((P.n + 31) / 32) * S * 64;
     if (total <= 0) return hipSuccess;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 32768) blocks = 32768;
-    if (P.dtype == 0) k_mfma_operands<0><<<(int)blocks, 256, 0, s>>>(P, kind, S, Pop, Qop);
-    else if (P.dtype == 1) k_mfma_operands<1><<<(int)blocks, 256, 0, s>>>(P, kind, S, Pop, Qop);
-    else k_mfma_operands<2><<<(int)blocks, 256, 0, s>>>(P, kind, S, Pop, Qop);
+    if (P.dtype == 0) k_mfma_operands<0><<<(int)blocks, 256, 0, s>>>(P, kind, S, scale, Pop, Qop);
+    else if (P.dtype == 1) k_mfma_operands<1><<<(int)blocks, 256, 0, s>>>(P, kind, S, scale, Pop, Qop);
+    else k_mfma_operands<2><<<(int)blocks, 256, 0, s>>>(P, kind, S, scale, Pop, Qop);
     return hipGetLastError();
 }
 
@@ -128,12 +136,12 @@ __device__ __forceinline__ float to_f32_up(double v)
     return f;
 }
 
-__global__ void k_mfma_scalars(int64_t n, const double *nu, MfmaBound b, double e2, double g64d, float *cinit,
-                               float *nuup, float *U, float *V, float *Z)
+__global__ void k_mfma_scalars(int64_t n, const double *nu, double nu_scale, MfmaBound b, double e2, double g64d,
+                               float *cinit, float *nuup, float *U, float *V, float *Z)
 {
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (r >= n) return;
-    const double v = nu[r];
+    const double v = nu[r] * nu_scale;                 // working units (exact power-of-two scale)
     const float nf = (float)v;
     cinit[r] = -0.5f * nf;
     nuup[r] = to_f32_up(v * (1.0 + g64d) * (1.0 + 1e-12));
@@ -153,12 +161,12 @@ __global__ void k_mfma_scalars(int64_t n, const double *nu, MfmaBound b, double 
     Z[r] = (float)((v - e2) * 0.5);
 }
 
-hipError_t launch_mfma_scalars(int64_t n, const double *nu, const MfmaBound &b, double e2, int d, float *cinit,
-                               float *nuup, float *U, float *V, float *Z, hipStream_t s)
+hipError_t launch_mfma_scalars(int64_t n, const double *nu, double nu_scale, const MfmaBound &b, double e2, int d,
+                               float *cinit, float *nuup, float *U, float *V, float *Z, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     const double g64d = (double)d * 0x1p-53 / (1.0 - (double)d * 0x1p-53);
-    k_mfma_scalars<<<(int)((n + 255) / 256), 256, 0, s>>>(n, nu, b, e2, g64d, cinit, nuup, U, V, Z);
+    k_mfma_scalars<<<(int)((n + 255) / 256), 256, 0, s>>>(n, nu, nu_scale, b, e2, g64d, cinit, nuup, U, V, Z);
     return hipGetLastError();
 }
 

@@ -23,11 +23,20 @@ def bf16_rne(x32):
     return (u.astype(np.uint32) << 16).view(np.float32)
 
 
-def operands(x64, path):
-    """Per point: (P, Q) operand vectors as float64 holding the exact 16-bit values."""
+def f16_scale(x64, stored_f16):
+    """Power of two s with max |s x| <= 2^15 (1 for float16 storage)."""
+    m = float(np.abs(x64).max())
+    if stored_f16 or m == 0.0:
+        return 1.0
+    return 2.0 ** (15 - np.frexp(m)[1])
+
+
+def operands(x64, path, scale=1.0):
+    """Per point: (P, Q) operand vectors as float64 holding the exact 16-bit values
+    (for f16, of the data scaled by `scale`: float32 rounding, then float16)."""
     x32 = x64.astype(np.float32)
     if path == "f16":
-        v = x64.astype(np.float16).astype(np.float64)
+        v = (x64 * scale).astype(np.float32).astype(np.float16).astype(np.float64)
         return v, v
     hi = bf16_rne(x32).astype(np.float64)
     if path == "bf16":
@@ -43,16 +52,22 @@ def fp32_sum(terms, order):
     return acc
 
 
-def check_pairs(points, pairs, path, eps=1.0, rng=None):
+def check_pairs(points, pairs, path, eps=1.0, rng=None, stored_f16=None):
+    """G is formed in working units (data times s, s a power of two, for the
+    scaled f16 path) and compared in data units against the reported bound."""
     rng = rng or np.random.default_rng(0)
     x = np.asarray(points, np.float64)
     d = x.shape[1]
     nu = np.einsum("ij,ij->i", x, x)
-    b = bm.error_bound(path, x.dtype if path != "f16" else np.float16, d, eps, nu.max(), np.abs(x).max())
-    P, Q = operands(x, path)
+    if stored_f16 is None:
+        stored_f16 = path == "f16"
+    dtype = np.float16 if stored_f16 else np.float32
+    b = bm.error_bound(path, dtype, d, eps, nu.max(), np.abs(x).max())
+    s = f16_scale(x, stored_f16) if path == "f16" else 1.0
+    P, Q = operands(x, path, s)
     worst = 0.0
     for a, p in pairs:
-        init = np.float32(-np.float32(nu[a]) / np.float32(2.0))
+        init = np.float32(-np.float32(nu[a] * s * s) / np.float32(2.0))
         terms = [float(init)] + list(Q[a] * P[p])
         h = -Fraction(nu[a]) / 2 + sum((Fraction(u) * Fraction(v) for u, v in zip(x[a], x[p])), Fraction(0))
         # exact norms for the bound's right-hand side
@@ -62,7 +77,7 @@ def check_pairs(points, pairs, path, eps=1.0, rng=None):
         n = len(terms)
         for order in (range(n), range(n - 1, -1, -1), rng.permutation(n)):
             g = fp32_sum(terms, order)
-            err = abs(Fraction(float(g)) - h)
+            err = abs(Fraction(float(g)) / Fraction(s * s) - h)
             assert err <= bound, f"{path}: |G-h| = {float(err)} > bound {float(bound)} (pair {a},{p})"
             if bound > 0:
                 worst = max(worst, float(err / bound))
@@ -84,6 +99,27 @@ def test_bound_f16_storage():
     x[:5, :3] = 3e-6                       # float16 subnormals
     pairs = [(int(i), int(j)) for i, j in rng.integers(0, 60, (150, 2))]
     check_pairs(x, pairs, "f16", eps=0.3, rng=rng)
+
+
+@pytest.mark.parametrize("scale", [1e-3, 1.0, 37.0, 3e4])
+def test_bound_f16_scaled(scale):
+    """float32 data of any magnitude on the f16 path: scaled by a power of two
+    into float16 range, rounded, and the bound reported back in data units."""
+    rng = np.random.default_rng(5)
+    x = (rng.standard_normal((60, 24)) * scale).astype(np.float32).astype(np.float64)
+    x[:4, :5] *= 1e-6                      # values that land among float16 subnormals
+    pairs = [(int(i), int(j)) for i, j in rng.integers(0, 60, (150, 2))] + [(i, i) for i in range(6)]
+    w = check_pairs(x, pairs, "f16", eps=scale, rng=rng, stored_f16=False)
+    assert w <= 1.0
+
+
+def test_bound_f16_scaled_worst_case():
+    """Every coordinate just under half a float16 spacing above 1 (after the
+    scale): all round down, all with the same sign."""
+    v = (1.0 + 2.0 ** -11 - 2.0 ** -20) * 2.0 ** -16      # scaled by 2^30 to just above 2^14
+    x = np.full((2, 7), v).astype(np.float32).astype(np.float64)
+    w = check_pairs(x, [(0, 1), (0, 0)], "f16", stored_f16=False)
+    assert 0.5 < w <= 1.0, w
 
 
 def test_bound_is_nearly_tight_for_bf16_worst_case():
@@ -123,7 +159,7 @@ def test_fp32_relative_bound():
 def test_delta_matches_definition():
     """delta is the additive radius error of Sec. 5.1 implied by the D-space bound."""
     b = bm.error_bound("bf16", np.float32, 32, 2.0, 50.0, 3.0)
-    w = 2 * ((b["alpha"] + b["beta"]) * 50.0 + b["abs_err"])
+    w = 2 * ((b["alpha"] + b["beta"]) * 50.0 + b["abs_err"]) + 2.0 ** -23 * (50.0 + 4.0)
     assert b["delta"] == pytest.approx(max(2.0 - np.sqrt(4.0 - w), np.sqrt(4.0 + w) - 2.0), rel=1e-12)
     assert b["exact_range"] == 1
     assert bm.error_bound("bf16", np.float32, 32, 1e-60, 50.0, 3.0)["exact_range"] == 0

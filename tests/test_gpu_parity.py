@@ -19,11 +19,11 @@ from paper_2601_01405_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-EXACT_PATHS = ["fp32", "bf16", "bf16x3", "auto"]
+EXACT_PATHS = ["fp32", "bf16", "bf16x3", "f16", "auto"]
 
 
 def paths_for(dtype):
-    return EXACT_PATHS + (["f16"] if np.dtype(dtype) == np.float16 else [])
+    return EXACT_PATHS
 
 
 def say(*a):

@@ -279,3 +279,13 @@ def test_threshold_is_rounded_in_double():
     res = oracle.build(x, eps)
     assert res.landmarks.tolist() == [0]
     assert res.row(0).tolist() == [0, 1]
+
+
+def test_first_member_matches_all_pairs_predicate():
+    x = W.clusters(400, 4, k=3, box=2.0, seed=8, dtype=np.float32)
+    res = oracle.build(x, 0.8)
+    mem = pairwise_s(x) < 0.8 * 0.8
+    got = oracle.first_member(x, res.landmarks, 0.8, np.arange(400))
+    for q in range(400):
+        hits = np.nonzero(mem[res.landmarks, q])[0]
+        assert got[q] == (hits[0] if hits.size else -1)
