@@ -41,6 +41,13 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed steps, run a plain copy kernel of known size (HBM counter calibration)")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("DB", "OUT"),
+                    help="write a kernel-trace summary of a rocprofv3 database and exit")
+    ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_DB", "WRITE_DB", "OUT"),
+                    help="write the range pass's HBM traffic per launch from two rocprofv3 --pmc databases")
+    ap.add_argument("--command", default="", help="the profiled command, recorded in a summary")
     return ap.parse_args()
 
 
@@ -74,8 +81,111 @@ def read_traffic(pairs_per_launch_known):
         return None
 
 
+# ---- rocprofv3 summaries (run on the host after a profiled bench run) -------------------
+PROBE_ELEMS = 1 << 26                    # float32: 256 MiB read + 256 MiB written per launch
+PROBE_BYTES = PROBE_ELEMS * 4
+
+
+def copy_probe():
+    """A plain elementwise kernel with known traffic, for scaling the counters."""
+    import torch
+    src = torch.ones(PROBE_ELEMS, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+
+
+def _template_args(name):
+    a = name.find("<")
+    b = name.find(">(")
+    return [t.strip() for t in name[a + 1:b].split(",")] if a >= 0 and b > a else []
+
+
+def is_range_pass(name):
+    """The membership range pass (not the candidate-block resolve, which
+    instantiates the same kernel with CONFLICT = true)."""
+    if "k_range_mfma<" not in name:
+        return False
+    ta = _template_args(name)
+    return len(ta) >= 3 and ta[2] == "false"
+
+
+def _dispatch_values(db, counter):
+    import sqlite3
+    con = sqlite3.connect(db)
+    per = {}
+    for name, disp, value in con.execute(
+            "select kernel_name, dispatch_id, value from counters_collection where counter_name = ?", (counter,)):
+        key = (name, disp)
+        per[key] = per.get(key, 0.0) + float(value)
+    con.close()
+    return per
+
+
+def summarize_traffic(fetch_db, write_db, out, command):
+    lines = ["# HBM traffic of the range pass (k_range_mfma, membership mode), from rocprofv3 counters",
+             f"# command (run twice, once per counter): {command}",
+             "# FETCH_SIZE and WRITE_SIZE are in KiB per dispatch; each is scaled by the factor that",
+             f"# makes it read {PROBE_BYTES} bytes for a plain copy kernel (torch.neg over {PROBE_ELEMS} float32)"]
+    res = {}
+    for counter, db in (("FETCH_SIZE", fetch_db), ("WRITE_SIZE", write_db)):
+        per = _dispatch_values(db, counter)
+        rng = [v for (name, _), v in per.items() if is_range_pass(name)]
+        probe = [v for (name, _), v in per.items() if "neg_kernel" in name]
+        if not rng or not probe:
+            raise SystemExit(f"{db}: {counter}: {len(rng)} range-pass and {len(probe)} probe dispatches")
+        f = PROBE_BYTES / (sum(probe) / len(probe) * 1024.0)
+        kib = sum(rng) / len(rng)
+        res[counter] = kib * 1024.0 * f
+        lines += [f"{counter.lower()}_range_dispatches = {len(rng)}",
+                  f"{counter.lower()}_kib_per_launch = {kib:.1f}",
+                  f"{counter.lower()}_probe_kib = {sum(probe) / len(probe):.1f}",
+                  f"{counter.lower()}_scale = {f:.5f}",
+                  f"{counter.lower()}_bytes_per_launch = {res[counter]:.0f}"]
+    lines += [f"kernel_source_sha256_16 = {kernel_hash()}",
+              f"hbm_bytes_per_launch = {res['FETCH_SIZE'] + res['WRITE_SIZE']:.0f}"]
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def summarize_trace(db, out, command):
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = {}
+    for name, start, end in con.execute("select name, start, \"end\" from kernels"):
+        key = name.split("(")[0].replace("void ", "")
+        if is_range_pass(name):
+            key += "  [range pass]"
+        c, t = rows.get(key, (0, 0.0))
+        rows[key] = (c + 1, t + (end - start) / 1e3)
+    con.close()
+    total = sum(t for _, t in rows.values()) or 1.0
+    lines = [f"# Kernel trace summary (rocprofv3 --kernel-trace --stats), durations in microseconds",
+             f"# command: {command}", "",
+             "| kernel | calls | total us | avg us | % |", "|---|---:|---:|---:|---:|"]
+    for key, (c, t) in sorted(rows.items(), key=lambda kv: -kv[1][1])[:25]:
+        lines.append(f"| {key} | {c} | {t:.0f} | {t / c:.2f} | {100 * t / total:.2f} |")
+    rp = [(c, t) for k, (c, t) in rows.items() if k.endswith("[range pass]")]
+    if rp:
+        c = sum(x for x, _ in rp)
+        t = sum(y for _, y in rp)
+        lines += ["", f"range pass: {c} launches, average {t / c:.2f} us"]
+    lines.append(f"kernel_source_sha256_16 = {kernel_hash()}")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     args = parse()
+    if args.summarize_traffic:
+        summarize_traffic(*args.summarize_traffic, args.command)
+        return
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace, args.command)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
@@ -202,6 +312,8 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+    if args.copy_probe:
+        copy_probe()
 
 
 if __name__ == "__main__":

@@ -102,8 +102,8 @@ typedef struct {
     double  ms_csr;               /* membership sort and row pointers                          */
     double  ms_edges;             /* edge build                                                */
     double  ms_download;          /* device-to-host copies of the results                      */
-    int64_t pairs_useful;         /* n_landmarks * n: the pairs the method must evaluate       */
-    int64_t pairs_issued;         /* pairs evaluated, including the candidate-block resolve    */
+    int64_t pairs_useful;         /* n_landmarks * n: every ball over every point (Sec. 2.2)   */
+    int64_t pairs_issued;         /* pairs evaluated: range passes + candidate-block resolve   */
     int64_t band_pairs;           /* pairs the low-precision filter could not decide           */
     int64_t blocks;               /* candidate blocks                                          */
     int64_t candidates;           /* candidates gathered over all blocks                       */
@@ -111,7 +111,9 @@ typedef struct {
     int32_t block;                /* block size actually used                                  */
     double  ms_range_kernel;      /* summed durations of the range-pass launches (profile = 1) */
     int64_t range_launches;       /* range-pass launches                                       */
-    int64_t range_pairs;          /* landmark-point pairs they evaluated                       */
+    int64_t range_pairs;          /* landmark-point pairs they evaluated; below pairs_useful
+                                     on the refined matrix-core paths, which skip earlier
+                                     landmarks (never in a later landmark's ball)             */
 } bm_stats;
 
 typedef struct {

@@ -380,7 +380,7 @@ bm_result *run_job(const Job &job, const bm_options &o)
         int32_t *lm_d = dev.alloc<int32_t>((size_t)lm_cap);
         int32_t *lm_rank = job.fixed ? lm_d : dev.alloc<int32_t>((size_t)lm_cap);   // fixed mode: ranks = indices
         int32_t *A = dev.alloc<int32_t>((size_t)B);
-        int64_t *fixtab = dev.alloc<int64_t>(2 * (size_t)kBlockLogSize);
+        int64_t *fixtab = dev.alloc<int64_t>(4 * 64);              // up to 64 rows of blk[0..3]
         GreedyState hs{};
         int64_t L = 0;
         RangeOut ro{nullptr, keys, cap, st, bn};
@@ -397,6 +397,7 @@ bm_result *run_job(const Job &job, const bm_options &o)
                 }
             }
         } ev_guard{evs};
+        SettledSet sd{};
         auto run_range = [&](const int32_t *Alist, const int64_t *blk, uint64_t *covered) {
             ro.keys = keys;
             ro.cap = cap;
@@ -411,7 +412,7 @@ bm_result *run_job(const Job &job, const bm_options &o)
             if (path == BM_PATH_FP32)
                 hip_ok(launch_range_fp32(xf, P, e2, thr32, o.refine, Alist, blk, B, ro, dev.s), "range_fp32");
             else
-                hip_ok(launch_range_mfma(ma, P, e2, Alist, blk, B, ro, dev.s), "range_mfma");
+                hip_ok(launch_range_mfma(ma, P, e2, Alist, blk, B, ro, sd, dev.s), "range_mfma");
             if (o.profile) hip_ok(hipEventRecord(e1, dev.s), "hipEventRecord");
             res->stats.range_launches++;
         };
@@ -436,11 +437,13 @@ bm_result *run_job(const Job &job, const bm_options &o)
                 const size_t m = std::min<size_t>(64, logs.size() - j);
                 dev.sync();
                 for (size_t q = 0; q < m; ++q) {
-                    tab_h[2 * q] = logs[j + q].L0;
-                    tab_h[2 * q + 1] = logs[j + q].na;
+                    tab_h[4 * q] = logs[j + q].L0;
+                    tab_h[4 * q + 1] = logs[j + q].na;
+                    tab_h[4 * q + 2] = logs[j + q].rlo;
+                    tab_h[4 * q + 3] = logs[j + q].m;
                 }
-                hip_ok(hipMemcpyAsync(fixtab, tab_h, m * 16, hipMemcpyHostToDevice, dev.s), "upload table");
-                for (size_t q = 0; q < m; ++q) run_range(lm_rank + logs[j + q].L0, fixtab + 2 * q, nullptr);
+                hip_ok(hipMemcpyAsync(fixtab, tab_h, m * 32, hipMemcpyHostToDevice, dev.s), "upload table");
+                for (size_t q = 0; q < m; ++q) run_range(lm_rank + logs[j + q].L0, fixtab + 4 * q, nullptr);
             }
             const GreedyState chk = dev.fetch(st);
             if (chk.nkeys != need) fail(BM_EINTERNAL, "membership count changed on recompute");
@@ -451,22 +454,24 @@ bm_result *run_job(const Job &job, const bm_options &o)
             // fixed-landmark mode: landmarks given as original indices (identity order)
             L = job.n_fixed;
             if (L > 0) hip_ok(hipMemcpyAsync(lm_d, job.fixed, (size_t)L * 4, hipMemcpyHostToDevice, dev.s), "upload lm");
-            std::vector<BlockLog> all;
-            for (int64_t a0 = 0; a0 < L; a0 += B) all.push_back(BlockLog{a0, std::min<int64_t>(B, L - a0), 0});
-            std::vector<BlockLog> pending;
+            std::vector<BlockLog> all;      // every rank scanned: rlo = 0, no settled list
+            for (int64_t a0 = 0; a0 < L; a0 += B) all.push_back(BlockLog{a0, std::min<int64_t>(B, L - a0), 0, 0, 0});
             for (size_t j = 0; j < all.size(); j += 64) {
                 const size_t m = std::min<size_t>(64, all.size() - j);
                 dev.sync();
                 for (size_t q = 0; q < m; ++q) {
-                    tab_h[2 * q] = all[j + q].L0;
-                    tab_h[2 * q + 1] = all[j + q].na;
+                    tab_h[4 * q] = all[j + q].L0;
+                    tab_h[4 * q + 1] = all[j + q].na;
+                    tab_h[4 * q + 2] = 0;
+                    tab_h[4 * q + 3] = 0;
                 }
-                hip_ok(hipMemcpyAsync(fixtab, tab_h, m * 16, hipMemcpyHostToDevice, dev.s), "upload table");
-                for (size_t q = 0; q < m; ++q) run_range(lm_d + all[j + q].L0, fixtab + 2 * q, nullptr);
+                hip_ok(hipMemcpyAsync(fixtab, tab_h, m * 32, hipMemcpyHostToDevice, dev.s), "upload table");
+                for (size_t q = 0; q < m; ++q) run_range(lm_d + all[j + q].L0, fixtab + 4 * q, nullptr);
             }
             hs = dev.fetch(st);
             if (hs.nkeys > cap) refill(all);    // all[0].nkeys_before = 0: recompute everything
             res->stats.blocks = (int64_t)all.size();
+            res->stats.range_pairs = L * n;
             res->stats.pairs_issued = L * n;
         } else if (n > 0) {
             const int nw = (B + 63) / 64;
@@ -492,6 +497,23 @@ bm_result *run_job(const Job &job, const bm_options &o)
                 cand_orig = dev.alloc<int32_t>((size_t)Bp);
             }
             const PointsView Pc{Xd, B, d, job.dtype, cand_orig};
+            // Settled list (refined matrix-core path): landmarks are skipped as
+            // points of later range passes, since no landmark is in another's ball.
+            // The unrefined predicate is not symmetric, so there every rank is scanned.
+            const bool settle = mfma_resolve && o.refine;
+            uint64_t *islm = nullptr;
+            if (settle) {
+                islm = dev.zeros<uint64_t>((size_t)((n + 63) / 64));
+                const size_t np = (size_t)((n + 31) / 32 * 32);
+                const size_t words = mfma_operand_words(n, ma.S);
+                sd.Pop = dev.zeros<uint16_t>(words);
+                float *th = dev.alloc<float>(3 * np);
+                hip_ok(hipMemsetD32Async((hipDeviceptr_t)th, 0x7f800000u, 3 * np, dev.s), "fill +inf");
+                sd.U = th;
+                sd.V = th + np;
+                sd.Z = th + 2 * np;
+                sd.idx = dev.zeros<int32_t>(np);
+            }
             BlockLog *blog = dev.alloc<BlockLog>(kBlockLogSize);
             std::vector<BlockLog> blog_h(kBlockLogSize);
             // Blocks are queued back to back; the host looks at the state once per batch.
@@ -500,6 +522,7 @@ bm_result *run_job(const Job &job, const bm_options &o)
                 const unsigned long long blocks_before = hs.blocks;
                 for (int k = 0; k < batch; ++k) {
                     hip_ok(launch_gather(covered, n, st, B, cand, rowflag, dev.s), "gather");
+                    if (settle) hip_ok(launch_settle(islm, st, cand, ma, sd, perm_d, dev.s), "settle");
                     if (mfma_resolve) {
                         hip_ok(launch_pack_candidates(ma, cand, st, perm_d, B, pk, cand_orig, dev.s), "pack");
                         hip_ok(launch_resolve_mfma(pk, Pc, &st->nc, e2, B, (uint32_t *)C, rowflag, st, dev.s),
@@ -507,7 +530,8 @@ bm_result *run_job(const Job &job, const bm_options &o)
                     } else {
                         hip_ok(launch_resolve_exact(P, e2, cand, st, B, C, rowflag, dev.s), "resolve");
                     }
-                    hip_ok(launch_accept(C, rowflag, cand, st, B, A, lm_d, lm_rank, blog, perm_d, dev.s), "accept");
+                    hip_ok(launch_accept(C, rowflag, cand, st, B, A, lm_d, lm_rank, blog, perm_d, islm, n, dev.s),
+                           "accept");
                     run_range(A, &st->L0, covered);
                 }
                 hs = dev.fetch(st);
@@ -535,7 +559,8 @@ bm_result *run_job(const Job &job, const bm_options &o)
             L = hs.L;
             res->stats.blocks = (int64_t)hs.blocks;
             res->stats.candidates = (int64_t)hs.candidates;
-            res->stats.pairs_issued = (int64_t)hs.resolve_pairs + L * n;
+            res->stats.range_pairs = (int64_t)hs.range_pairs;
+            res->stats.pairs_issued = (int64_t)hs.resolve_pairs + (int64_t)hs.range_pairs;
         }
         dev.sync();
         for (auto &e : evs) {
@@ -545,7 +570,6 @@ bm_result *run_job(const Job &job, const bm_options &o)
         }
         res->stats.band_pairs = (int64_t)hs.band;
         res->stats.pairs_useful = L * n;
-        res->stats.range_pairs = L * n;
         res->stats.ms_greedy = ms_since(t_greedy);
 
         // -- membership CSR

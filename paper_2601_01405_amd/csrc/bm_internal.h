@@ -20,8 +20,10 @@ struct PointsView {
 // back; the host reads it once per batch of blocks.
 struct GreedyState {
     int64_t cursor;                 // every rank < cursor is a landmark or covered
-    int64_t L0;                     // ordinal of this block's first landmark   } read by the range
-    int64_t na;                     // candidates accepted in this block         } pass as blk[0..1]
+    int64_t L0;                     // ordinal of this block's first landmark      } read by the
+    int64_t na;                     // candidates accepted in this block            } range pass
+    int64_t rlo;                    // ranks >= rlo (a multiple of 32) are scanned  } as blk[0..3]
+    int64_t m;                      // settled non-landmarks (ranks < rlo) listed   }
     int64_t L;                      // landmarks so far
     int32_t nc;                     // candidates gathered in this block
     int32_t done;                   // 1 once a gather found no uncovered rank
@@ -33,13 +35,26 @@ struct GreedyState {
     unsigned long long blocks;      // blocks with at least one candidate
     unsigned long long candidates;  // candidates over all blocks
     unsigned long long resolve_pairs;
+    unsigned long long range_pairs; // landmark-point pairs the range passes computed
 };
 
 // Per-block record for recomputing a block's memberships after the key
 // buffer overflowed: its first ordinal, accepted count and key count before it.
 struct BlockLog {
-    int64_t L0, na;
+    int64_t L0, na, rlo, m;         // the range pass's blk[0..3]
     unsigned long long nkeys_before;
+};
+
+// Settled non-landmarks.  In refined mode a landmark is never in another
+// landmark's ball (the net is separated and the exact predicate is symmetric),
+// so a block's range pass need not look at earlier landmarks: it scans every
+// rank >= rlo (rlo = the block's first candidate rounded down to a tile) and,
+// below rlo, only this compacted list of covered non-landmarks, in rank order.
+// Entries >= m carry +inf thresholds and zero operands.
+struct SettledSet {
+    uint16_t *Pop;                  // point-side operands, swizzled like MfmaArgs::Pop
+    float *U, *V, *Z;               // thresholds copied from the rank arrays
+    int32_t *idx;                   // original row index of entry j
 };
 constexpr int kBlockLogSize = 256;
 

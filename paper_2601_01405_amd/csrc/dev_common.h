@@ -7,6 +7,8 @@
 
 namespace bm {
 
+typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
+
 // ---- exact widening of a stored coordinate -------------------------------------------
 template <int DT>
 __device__ __forceinline__ double load_coord(const void *X, int64_t off)

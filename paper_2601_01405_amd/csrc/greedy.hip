@@ -117,7 +117,7 @@ constexpr int MAX_B = 4096;
 __global__ __launch_bounds__(ACCEPT_THREADS) void k_accept(const uint64_t *C, const int *rowflag, int nw,
                                                            const int32_t *cand, GreedyState *st, int32_t *A,
                                                            int32_t *landmarks, int32_t *lm_rank, BlockLog *blog,
-                                                           const int32_t *perm)
+                                                           const int32_t *perm, uint64_t *islm, int64_t n)
 {
     const int64_t L0 = st->L;
     __shared__ unsigned long long acc[MAX_B / 64], rej[MAX_B / 64];
@@ -174,6 +174,7 @@ __global__ __launch_bounds__(ACCEPT_THREADS) void k_accept(const uint64_t *C, co
             A[pos] = r;
             landmarks[L0 + pos] = perm ? perm[r] : r;
             lm_rank[L0 + pos] = r;
+            if (islm) atomicOr((unsigned long long *)&islm[r >> 6], 1ull << (r & 63));
             ++pos;
         }
     }
@@ -182,10 +183,13 @@ __global__ __launch_bounds__(ACCEPT_THREADS) void k_accept(const uint64_t *C, co
         st->na = total;
         st->L = L0 + total;
         st->rounds += rounds;
+        st->range_pairs += (unsigned long long)total * (unsigned long long)(st->m + n - st->rlo);
         if (nc > 0) {
             BlockLog &b = blog[(st->blocks - 1) % kBlockLogSize];
             b.L0 = L0;
             b.na = total;
+            b.rlo = st->rlo;
+            b.m = st->m;
             b.nkeys_before = st->nkeys;
         }
     }
@@ -193,10 +197,66 @@ __global__ __launch_bounds__(ACCEPT_THREADS) void k_accept(const uint64_t *C, co
 
 hipError_t launch_accept(const uint64_t *C, const int *rowflag, const int32_t *cand, GreedyState *st, int B,
                          int32_t *A, int32_t *landmarks, int32_t *lm_rank, BlockLog *blog, const int32_t *perm,
-                         hipStream_t s)
+                         uint64_t *islm, int64_t n, hipStream_t s)
 {
     if (B > MAX_B) return hipErrorInvalidValue;
-    k_accept<<<1, ACCEPT_THREADS, 0, s>>>(C, rowflag, (B + 63) / 64, cand, st, A, landmarks, lm_rank, blog, perm);
+    k_accept<<<1, ACCEPT_THREADS, 0, s>>>(C, rowflag, (B + 63) / 64, cand, st, A, landmarks, lm_rank, blog, perm,
+                                          islm, n);
+    return hipGetLastError();
+}
+
+// Settling, run after a gather: every rank below the new block's first
+// candidate is final (a landmark, or covered and never a landmark).  The
+// non-landmarks among ranks [rlo, R), R = that candidate rounded down to a
+// tile, are appended in rank order to the settled list (their point-side
+// operands, thresholds and original index), and rlo becomes R.
+constexpr int SETTLE_THREADS = 1024;
+
+__global__ __launch_bounds__(SETTLE_THREADS) void k_settle(const uint64_t *islm, GreedyState *st, const int32_t *cand,
+                                                           MfmaArgs a, SettledSet out, const int32_t *perm)
+{
+    __shared__ int sh_scan[SETTLE_THREADS / 64];
+    __shared__ int32_t sel[SETTLE_THREADS];
+    const int nc = st->nc;
+    if (nc == 0) return;                                   // workgroup-uniform
+    const int64_t R0 = st->rlo;
+    const int64_t R1 = ((int64_t)cand[0] >> 5) << 5;
+    int64_t m = st->m;
+    const int S = a.S, nvec = 2 * S;
+    for (int64_t r0 = R0; r0 < R1; r0 += SETTLE_THREADS) {
+        const int64_t r = r0 + threadIdx.x;
+        const bool take = r < R1 && !((islm[r >> 6] >> (r & 63)) & 1ull);
+        int total;
+        const int pre = block_excl_scan<SETTLE_THREADS>((int)take, &total, sh_scan);
+        if (take) {
+            const int64_t j = m + pre;
+            sel[pre] = (int32_t)r;
+            out.U[j] = a.U[r];
+            out.V[j] = a.V[r];
+            out.Z[j] = a.Z[r];
+            out.idx[j] = perm ? perm[r] : (int32_t)r;
+        }
+        __syncthreads();
+        for (int v = threadIdx.x; v < total * nvec; v += SETTLE_THREADS) {
+            const int q = v / nvec, rem = v - q * nvec, ss = rem >> 1, half = rem & 1;
+            const int64_t src = sel[q], dst = m + q;
+            const int64_t so = ((((src >> 5) * S + ss) * 64) + (src & 31) + 32 * half) * 8;
+            const int64_t dof = ((((dst >> 5) * S + ss) * 64) + (dst & 31) + 32 * half) * 8;
+            *(u32x4 *)(out.Pop + dof) = *(const u32x4 *)(a.Pop + so);
+        }
+        m += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        st->rlo = R1;
+        st->m = m;
+    }
+}
+
+hipError_t launch_settle(const uint64_t *islm, GreedyState *st, const int32_t *cand, const MfmaArgs &a,
+                         const SettledSet &out, const int32_t *perm, hipStream_t s)
+{
+    k_settle<<<1, SETTLE_THREADS, 0, s>>>(islm, st, cand, a, out, perm);
     return hipGetLastError();
 }
 

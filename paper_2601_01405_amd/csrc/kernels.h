@@ -39,7 +39,10 @@ hipError_t launch_resolve_exact(const PointsView &P, double e2, const int32_t *c
 // at ordinal st->L, and records the block in blog[st->blocks % kBlockLogSize].
 hipError_t launch_accept(const uint64_t *C, const int *rowflag, const int32_t *cand, GreedyState *st, int B,
                          int32_t *A, int32_t *landmarks, int32_t *lm_rank, BlockLog *blog, const int32_t *perm,
-                         hipStream_t s);
+                         uint64_t *islm, int64_t n, hipStream_t s);
+// After a gather: append the settled non-landmarks below the block's first candidate.
+hipError_t launch_settle(const uint64_t *islm, GreedyState *st, const int32_t *cand, const MfmaArgs &a,
+                         const SettledSet &out, const int32_t *perm, hipStream_t s);
 
 // ---- range passes -----------------------------------------------------------------------
 // Range pass of landmarks A[0..blk[1]) (ranks) with ordinals blk[0] + i;
@@ -60,8 +63,10 @@ hipError_t launch_range_fp32(const float *xf, const PointsView &P, double e2, Fp
 
 // One-wave check of the matrix-core layout and subnormal handling (flags, see range_mfma.hip).
 hipError_t run_selfcheck(int *flags_dev, hipStream_t s);
+// blk[0..3] = first ordinal, landmark count, rlo, settled count (see SettledSet);
+// rlo = 0 and a zero count scan every rank.
 hipError_t launch_range_mfma(const MfmaArgs &a, const PointsView &P, double e2, const int32_t *A,
-                             const int64_t *blk, int na_max, const RangeOut &o, hipStream_t s);
+                             const int64_t *blk, int na_max, const RangeOut &o, const SettledSet &sd, hipStream_t s);
 // Candidate-block resolve on the matrix cores: `packed` holds the candidates'
 // operands and scalars in candidate order, Pc.perm their original indices;
 // writes the conflict words (as 32-bit halves) and row flags.

@@ -25,7 +25,6 @@ namespace bm {
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(8))) _Float16 f16x8;
-typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 
 // ---- operand preparation --------------------------------------------------------------
@@ -214,11 +213,17 @@ __host__ __device__ constexpr int stage_tiles(bool chunked, int ks)
 // Staging vectors per thread for one stage: TPS tiles of S steps plus 96 thresholds each.
 __host__ __device__ constexpr int stage_slots(int S, int tps) { return (tps * (S * 64 + 96) + RM_THREADS - 1) / RM_THREADS; }
 
+// Point space of a MEMBERS pass: tiles [0, MT) are the settled list (entries
+// < m valid), then rank tiles from rlo / 32 to the end.  A CONFLICT pass has
+// no settled part.  The grid is NGW landmark groups x `chunks` point chunks
+// (chunks a multiple of 8); the chunk length follows the device-side tile
+// count.  Workgroups are dispatched to the 8 XCDs round robin, so the NGW
+// groups of one chunk are placed on the same XCD and share its L2.
 template <int KS, bool F16, bool CONFLICT, int SLOTS, bool CHUNKED>
 __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsView P, const int32_t *n_dev, double e2,
                                                            const int32_t *__restrict__ A, const int64_t *blk,
-                                                           RangeOut o, uint32_t *C32, int c32_stride, int *rowflag,
-                                                           int NGW, int64_t tpc, int nch)
+                                                           RangeOut o, SettledSet sd, uint32_t *C32, int c32_stride,
+                                                           int *rowflag, int NGW, int chunks, int nch)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int S = a.S;
@@ -233,13 +238,20 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
     const int64_t n = n_dev ? (int64_t)*n_dev : P.n;
     const int64_t ord0 = CONFLICT ? 0 : blk[0];
     const int na = CONFLICT ? (int)n : (int)blk[1];
+    const int64_t msz = CONFLICT ? 0 : blk[3];                     // settled entries
+    const int64_t MT = (msz + 31) / 32;                            // settled tiles
+    const int64_t RT0 = CONFLICT ? 0 : (blk[2] >> 5);              // first rank tile
     const int wid = (int)(threadIdx.x >> 6), lane = lane_id(), col = lane & 31, half = lane >> 5;
-    const int g = (int)(blockIdx.x % NGW);
-    const int64_t c = blockIdx.x / NGW;
+    const int xcd = (int)(blockIdx.x & 7);
+    const int kk = (int)(blockIdx.x >> 3);
+    const int g = kk % NGW;
+    const int64_t c = (int64_t)(kk / NGW) * 8 + xcd;
     if (g * RM_WAVES * RM_MP * 32 >= na) return;                   // workgroup-uniform
     const int64_t NT = (n + 31) / 32;
+    const int64_t CT = MT + NT - RT0;                              // tiles of the point space
+    const int64_t tpc = (CT + chunks - 1) / chunks;
     const int64_t t0 = c * tpc;
-    const int64_t t1 = min(NT, t0 + tpc);
+    const int64_t t1 = min(CT, t0 + tpc);
     if (t0 >= t1) return;                                          // workgroup-uniform
     const int pbase = (g * RM_WAVES + wid) * RM_MP;                // first panel of this wave
     const bool live = pbase * 32 < na;                             // wave-uniform
@@ -312,13 +324,16 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
                 const int tt = it / tile_items, r = it - tt * tile_items;
                 const int64_t t = ts + tt;
                 if (t < t1) {
+                    const bool settled = t < MT;
+                    const int64_t ts_ = settled ? t : RT0 + (t - MT);        // tile in its own array
                     if (r < buf_words) {
-                        v = *(const u32x4 *)(a.Pop + ((t * S) * 64 + r) * 8);
+                        v = *(const u32x4 *)((settled ? sd.Pop : a.Pop) + ((ts_ * S) * 64 + r) * 8);
                     } else {
                         const int q = r - buf_words, which = q >> 5;
-                        const int64_t pt = t * 32 + (q & 31);
+                        const int64_t pt = ts_ * 32 + (q & 31);
                         float f = INFINITY;
-                        if (pt < n) f = which == 0 ? a.U[pt] : which == 1 ? a.V[pt] : a.Z[pt];
+                        if (settled) f = which == 0 ? sd.U[pt] : which == 1 ? sd.V[pt] : sd.Z[pt];
+                        else if (pt < n) f = which == 0 ? a.U[pt] : which == 1 ? a.V[pt] : a.Z[pt];
                         v[0] = __float_as_uint(f);
                     }
                 }
@@ -356,8 +371,10 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
         if (t >= t1) break;                                             // wave-uniform
         const int sb = (buf * TPS + tt) * buf_words;                    // this tile's operands in LDS
         const int stt = (buf * TPS + tt) * 96;                          // and thresholds
-        const int64_t p = t * 32 + col;
-        const bool pv = p < n;
+        const bool settled = t < MT;                                    // wave-uniform
+        const int64_t tr = settled ? t : RT0 + (t - MT);                // tile in its own array
+        const int64_t p = tr * 32 + col;                                // settled entry or rank
+        const bool pv = settled ? p < msz : p < n;
         const float Ux = sT[stt + col], Vx = sT[stt + 32 + col], Zx = sT[stt + 64 + col];
         f32x16 acc[RM_MP];
         if (!CHUNKED) {
@@ -410,7 +427,7 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
                 if (!__ballot(!(m <= cut))) continue;
             }
             uint32_t mem = 0;
-            const int64_t xo = pv ? orig_index(P, p) : 0;
+            const int64_t xo = !pv ? 0 : settled ? (int64_t)sd.idx[p] : orig_index(P, p);
             if (a.refine) {
                 const float v = Vx + aw[pi];
                 uint32_t bnd = 0;
@@ -469,11 +486,11 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
                 ++base;
             }
         }
-        if (!CONFLICT && o.covered) {
+        if (!CONFLICT && o.covered && !settled) {
             const uint64_t m = __ballot(cov);
             const uint64_t bits = (m | (m >> 32)) & 0xffffffffull;
             if (bits && lane == 0)
-                atomicOr((unsigned long long *)&o.covered[(t * 32) >> 6], (unsigned long long)(bits << ((t * 32) & 63)));
+                atomicOr((unsigned long long *)&o.covered[(tr * 32) >> 6], (unsigned long long)(bits << ((tr * 32) & 63)));
         }
       }
     }
@@ -541,13 +558,13 @@ hipError_t run_selfcheck(int *flags_dev, hipStream_t s)
 
 template <int KS, bool F16, bool CONFLICT, int SLOTS, bool CHUNKED>
 static hipError_t launch_ks(const MfmaArgs &a, const PointsView &P, const int32_t *n_dev, double e2, const int32_t *A,
-                            const int64_t *blk, int na_max, int64_t n_max, const RangeOut &o, uint32_t *C32,
-                            int c32_stride, int *rowflag, int nch, hipStream_t s)
+                            const int64_t *blk, int na_max, int64_t n_max, const RangeOut &o, const SettledSet &sd,
+                            uint32_t *C32, int c32_stride, int *rowflag, int nch, hipStream_t s)
 {
     const int npan = (na_max + 31) / 32;
     const int per_wg = RM_WAVES * RM_MP;
     const int NGW = (npan + per_wg - 1) / per_wg;
-    const int64_t NT = (n_max + 31) / 32;
+    const int64_t NT = (n_max + 31) / 32 + 1;                      // + a partial settled tile
     // about one workgroup per CU (256 CUs) unless BM_RANGE_WORKGROUPS says otherwise
     static const int64_t env_wg = [] {
         const char *e = getenv("BM_RANGE_WORKGROUPS");
@@ -556,24 +573,23 @@ static hipError_t launch_ks(const MfmaArgs &a, const PointsView &P, const int32_
     const int64_t target_wg = env_wg > 0 ? env_wg : 256;
     int64_t chunks = (target_wg + NGW - 1) / NGW;
     if (chunks > NT) chunks = NT;
-    if (chunks < 1) chunks = 1;
-    const int64_t tpc = (NT + chunks - 1) / chunks;
-    chunks = (NT + tpc - 1) / tpc;
+    chunks = (chunks + 7) / 8 * 8;                                  // whole XCD rounds
     const int64_t wgs = (int64_t)NGW * chunks;
     constexpr int TPS = stage_tiles(CHUNKED, KS);
     const size_t shmem = (size_t)2 * TPS * (a.S * 64 * 16 + 96 * sizeof(float)) + 2 * RM_THREADS * sizeof(float);
-    k_range_mfma<KS, F16, CONFLICT, SLOTS, CHUNKED><<<(unsigned)wgs, RM_THREADS, shmem, s>>>(a, P, n_dev, e2, A, blk, o, C32, c32_stride,
-                                                                          rowflag, NGW, tpc, nch);
+    k_range_mfma<KS, F16, CONFLICT, SLOTS, CHUNKED><<<(unsigned)wgs, RM_THREADS, shmem, s>>>(
+        a, P, n_dev, e2, A, blk, o, sd, C32, c32_stride, rowflag, NGW, (int)chunks, nch);
     return hipGetLastError();
 }
 
 template <bool F16, bool CONFLICT>
 static hipError_t dispatch(const MfmaArgs &a, const PointsView &P, const int32_t *n_dev, double e2, const int32_t *A,
-                           const int64_t *blk, int na_max, int64_t n_max, const RangeOut &o, uint32_t *C32,
-                           int c32_stride, int *rowflag, hipStream_t s)
+                           const int64_t *blk, int na_max, int64_t n_max, const RangeOut &o, const SettledSet &sd,
+                           uint32_t *C32, int c32_stride, int *rowflag, hipStream_t s)
 {
 #define BM_KS(k, nch, slots) \
-    launch_ks<k, F16, CONFLICT, slots, (nch > 1)>(a, P, n_dev, e2, A, blk, na_max, n_max, o, C32, c32_stride, rowflag, nch, s)
+    launch_ks<k, F16, CONFLICT, slots, (nch > 1)>(a, P, n_dev, e2, A, blk, na_max, n_max, o, sd, C32, c32_stride, rowflag, \
+                                                  nch, s)
     switch (a.S) {
     case 1: return BM_KS(1, 1, stage_slots(1, stage_tiles(false, 1)));
     case 2: return BM_KS(2, 1, stage_slots(2, stage_tiles(false, 2)));
@@ -584,18 +600,19 @@ static hipError_t dispatch(const MfmaArgs &a, const PointsView &P, const int32_t
     case 7: return BM_KS(7, 1, stage_slots(7, stage_tiles(false, 7)));
     case 8: return BM_KS(8, 1, stage_slots(8, stage_tiles(false, 8)));
     default: return launch_ks<8, F16, CONFLICT, stage_slots(kMaxMfmaSteps, stage_tiles(true, 8)), true>(
-                 a, P, n_dev, e2, A, blk, na_max, n_max, o, C32, c32_stride, rowflag, (a.S + 7) / 8, s);
+                 a, P, n_dev, e2, A, blk, na_max, n_max, o, sd, C32, c32_stride, rowflag, (a.S + 7) / 8, s);
     }
 #undef BM_KS
 }
 
 hipError_t launch_range_mfma(const MfmaArgs &a, const PointsView &P, double e2, const int32_t *A,
-                             const int64_t *blk, int na_max, const RangeOut &o, hipStream_t s)
+                             const int64_t *blk, int na_max, const RangeOut &o, const SettledSet &sd, hipStream_t s)
 {
     if (a.S > kMaxMfmaSteps) return hipErrorInvalidValue;
     if (P.n <= 0 || na_max <= 0) return hipSuccess;
-    if (a.kind == MFMA_F16) return dispatch<true, false>(a, P, nullptr, e2, A, blk, na_max, P.n, o, nullptr, 0, nullptr, s);
-    return dispatch<false, false>(a, P, nullptr, e2, A, blk, na_max, P.n, o, nullptr, 0, nullptr, s);
+    if (a.kind == MFMA_F16)
+        return dispatch<true, false>(a, P, nullptr, e2, A, blk, na_max, P.n, o, sd, nullptr, 0, nullptr, s);
+    return dispatch<false, false>(a, P, nullptr, e2, A, blk, na_max, P.n, o, sd, nullptr, 0, nullptr, s);
 }
 
 hipError_t launch_resolve_mfma(const MfmaArgs &packed, const PointsView &Pc, const int32_t *nc_dev, double e2, int B,
@@ -603,10 +620,11 @@ hipError_t launch_resolve_mfma(const MfmaArgs &packed, const PointsView &Pc, con
 {
     if (packed.S > kMaxMfmaSteps) return hipErrorInvalidValue;
     RangeOut o{nullptr, nullptr, 0, st, 0};
+    const SettledSet none{};
     const int stride = 2 * ((B + 63) / 64);
     if (packed.kind == MFMA_F16)
-        return dispatch<true, true>(packed, Pc, nc_dev, e2, nullptr, nullptr, B, B, o, C32, stride, rowflag, s);
-    return dispatch<false, true>(packed, Pc, nc_dev, e2, nullptr, nullptr, B, B, o, C32, stride, rowflag, s);
+        return dispatch<true, true>(packed, Pc, nc_dev, e2, nullptr, nullptr, B, B, o, none, C32, stride, rowflag, s);
+    return dispatch<false, true>(packed, Pc, nc_dev, e2, nullptr, nullptr, B, B, o, none, C32, stride, rowflag, s);
 }
 
 // Copy the gathered candidates' operands and scalars into a packed set

@@ -185,3 +185,24 @@ def test_paper_gaussian_worked_example():
 def test_device_selfcheck():
     """Matrix-core output layout and exact subnormal operands, as the bound assumes."""
     assert bm.device_selfcheck() == 15
+
+
+def test_range_pair_accounting():
+    """Refined matrix-core passes skip earlier landmarks as points (none is in a
+    later landmark's ball), so they compute between L(n-L+1) and L n pairs;
+    the FP32 path and the unrefined mode scan every point."""
+    n = 5000
+    x = W.clusters(n, 8, k=4, box=6.0, seed=11, dtype=np.float32)
+    ref = oracle.build(x, 0.8)
+    for path in ("fp32", "bf16x3", "f16"):
+        say("accounting n=5000 d=8 eps=0.8", path)
+        r = bm.build(x, 0.8, path=path, block=128)
+        assert_same(r, ref, f"accounting {path}")
+        L, s = r.n_landmarks, r.stats
+        assert s["pairs_useful"] == L * n
+        if path == "fp32":
+            assert s["range_pairs"] == L * n
+        else:
+            assert L * (n - L + 1) <= s["range_pairs"] < L * n
+        u = bm.build(x, 0.8, path=path, block=128, refine=False)
+        assert u.stats["range_pairs"] == u.n_landmarks * n
