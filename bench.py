@@ -254,6 +254,14 @@ def main():
     range_pairs = sum(s["range_pairs"] for run in runs for s, _, _ in run)
     log(f"refined {used_path}: {value:.1f} G pair-dists/s, {elapsed / args.steps * 1e3:.2f} ms/step, "
         f"range kernels {range_ms / args.steps:.2f} ms/step over {launches // args.steps} launches")
+    # the same steps without the per-dispatch events, to show what timing them costs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(args.path)
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t0) / args.steps * 1e3
+    log(f"same steps without kernel events: {plain_ms:.2f} ms/step")
 
     # -- plain FP32 path on the same inputs
     fp32 = None
@@ -304,6 +312,7 @@ def main():
         "config": {"workload": args.workload, "n": n, "d": d, "storage": str(x.dtype), "eps": eps_list,
                    "path": used_path, "block": block, "order": "index"},
         "graph_ms": graph_ms,
+        "ms_per_step_without_events": plain_ms,
         "landmarks": [s[1] for s in runs[0]], "edges": [s[2] for s in runs[0]],
         "fp32_path": fp32,
         "speedup_vs_fp32": (value / fp32["value"]) if fp32 else None,

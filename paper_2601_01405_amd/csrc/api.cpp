@@ -349,17 +349,13 @@ bm_result *run_job(const Job &job, const bm_options &o)
             const double sc2 = scale * scale;
             const MfmaBound mb = mfma_bound(kind, d, 16 * S, e2 * sc2, std::sqrt(max_nu) * scale, max_abs * scale,
                                             (flags & 4) != 0, job.dtype == BM_F16);
-            float *sc = dev.alloc<float>((size_t)n * 5);
-            hip_ok(launch_mfma_scalars(n, nu, sc2, mb, e2 * sc2, d, sc, sc + n, sc + 2 * n, sc + 3 * n, sc + 4 * n,
-                                       dev.s),
-                   "mfma_scalars");
+            float *sc = dev.alloc<float>((size_t)n * 2 + t3_floats(n));
+            hip_ok(launch_mfma_scalars(n, nu, sc2, mb, e2 * sc2, d, sc, sc + n, sc + 2 * n, dev.s), "mfma_scalars");
             ma.Pop = Pop;
             ma.Qop = Qop;
             ma.cinit = sc;
             ma.nuup = sc + n;
-            ma.U = sc + 2 * n;
-            ma.V = sc + 3 * n;
-            ma.Z = sc + 4 * n;
+            ma.T3 = sc + 2 * n;
             ma.alpha = f32_up(mb.alpha);
             ma.S = S;
             ma.kind = kind;
@@ -407,13 +403,12 @@ bm_result *run_job(const Job &job, const bm_options &o)
                 hip_ok(hipEventCreate(&e0), "hipEventCreate");
                 hip_ok(hipEventCreate(&e1), "hipEventCreate");
                 evs.emplace_back(e0, e1);
-                hip_ok(hipEventRecord(e0, dev.s), "hipEventRecord");
             }
+            const LaunchEvents ev{e0, e1};     // the dispatch's own start and end
             if (path == BM_PATH_FP32)
-                hip_ok(launch_range_fp32(xf, P, e2, thr32, o.refine, Alist, blk, B, ro, dev.s), "range_fp32");
+                hip_ok(launch_range_fp32(xf, P, e2, thr32, o.refine, Alist, blk, B, ro, dev.s, ev), "range_fp32");
             else
-                hip_ok(launch_range_mfma(ma, P, e2, Alist, blk, B, ro, sd, dev.s), "range_mfma");
-            if (o.profile) hip_ok(hipEventRecord(e1, dev.s), "hipEventRecord");
+                hip_ok(launch_range_mfma(ma, P, e2, Alist, blk, B, ro, sd, dev.s, ev), "range_mfma");
             res->stats.range_launches++;
         };
         // The key buffer overflowed: grow it, then recompute the memberships of
@@ -488,12 +483,10 @@ bm_result *run_job(const Job &job, const bm_options &o)
                 const size_t words = mfma_operand_words(Bp, ma.S);
                 pk.Pop = dev.alloc<uint16_t>(words);
                 pk.Qop = (ma.Qop != ma.Pop) ? dev.alloc<uint16_t>(words) : pk.Pop;
-                float *psc = dev.alloc<float>((size_t)Bp * 5);
+                float *psc = dev.alloc<float>((size_t)Bp * 2 + t3_floats(Bp));
                 pk.cinit = psc;
                 pk.nuup = psc + Bp;
-                pk.U = psc + 2 * Bp;
-                pk.V = psc + 3 * Bp;
-                pk.Z = psc + 4 * Bp;
+                pk.T3 = psc + 2 * Bp;
                 cand_orig = dev.alloc<int32_t>((size_t)Bp);
             }
             const PointsView Pc{Xd, B, d, job.dtype, cand_orig};
@@ -507,11 +500,8 @@ bm_result *run_job(const Job &job, const bm_options &o)
                 const size_t np = (size_t)((n + 31) / 32 * 32);
                 const size_t words = mfma_operand_words(n, ma.S);
                 sd.Pop = dev.zeros<uint16_t>(words);
-                float *th = dev.alloc<float>(3 * np);
-                hip_ok(hipMemsetD32Async((hipDeviceptr_t)th, 0x7f800000u, 3 * np, dev.s), "fill +inf");
-                sd.U = th;
-                sd.V = th + np;
-                sd.Z = th + 2 * np;
+                sd.T3 = dev.alloc<float>(t3_floats(n));
+                hip_ok(hipMemsetD32Async((hipDeviceptr_t)sd.T3, 0x7f800000, t3_floats(n), dev.s), "fill +inf");
                 sd.idx = dev.zeros<int32_t>(np);
             }
             BlockLog *blog = dev.alloc<BlockLog>(kBlockLogSize);

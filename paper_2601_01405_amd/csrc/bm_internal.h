@@ -53,7 +53,7 @@ struct BlockLog {
 // Entries >= m carry +inf thresholds and zero operands.
 struct SettledSet {
     uint16_t *Pop;                  // point-side operands, swizzled like MfmaArgs::Pop
-    float *U, *V, *Z;               // thresholds copied from the rank arrays
+    float *T3;                      // thresholds, tiled like MfmaArgs::T3
     int32_t *idx;                   // original row index of entry j
 };
 constexpr int kBlockLogSize = 256;
@@ -82,6 +82,11 @@ inline size_t mfma_operand_words(int64_t points, int S)
     return (size_t)((points + 31) / 32) * (size_t)S * 64 * 8;
 }
 
+enum { T3_U = 0, T3_V = 1, T3_Z = 2 };
+__host__ __device__ inline int64_t t3_index(int64_t r, int which) { return (r >> 5) * 96 + which * 32 + (r & 31); }
+// floats of a tiled threshold array for `points` points
+inline size_t t3_floats(int64_t points) { return (size_t)((points + 31) / 32) * 96; }
+
 // Constants of the MFMA error bound (host computed, see bounds.h).  The kernel
 // output for landmark a and point x is  G = -RN32(nu_a)/2 + sum_k P_k Q_k, an
 // estimate of (nu_x - D)/2, and |G - (nu_x - D)/2| <= alpha nu_a + beta nu_x + abs.
@@ -96,9 +101,11 @@ struct MfmaArgs {
     const uint16_t *Qop;            // landmark-side operands, swizzled
     const float *cinit;             // per rank: -RN32(nu)/2
     const float *nuup;              // per rank: nu rounded up
-    const float *U;                 // per rank: G <= U - alpha*nu_a  =>  not a member
-    const float *V;                 // per rank: G >  V + alpha*nu_a  =>  member
-    const float *Z;                 // per rank: unrefined decision G > Z
+    // Decision thresholds, tiled per 32 ranks: tile t holds U[32], V[32], Z[32]
+    // (t3_index); padding ranks hold +inf.
+    //   G <= U - alpha*nu_a  =>  not a member;   G > V + alpha*nu_a  =>  member;
+    //   unrefined: member iff G > Z.
+    const float *T3;
     float alpha;                    // rounded up
     int32_t S;                      // K / 16
     int32_t kind;

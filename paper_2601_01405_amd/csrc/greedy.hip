@@ -231,9 +231,8 @@ __global__ __launch_bounds__(SETTLE_THREADS) void k_settle(const uint64_t *islm,
         if (take) {
             const int64_t j = m + pre;
             sel[pre] = (int32_t)r;
-            out.U[j] = a.U[r];
-            out.V[j] = a.V[r];
-            out.Z[j] = a.Z[r];
+#pragma unroll
+            for (int w = 0; w < 3; ++w) out.T3[t3_index(j, w)] = a.T3[t3_index(r, w)];
             out.idx[j] = perm ? perm[r] : (int32_t)r;
         }
         __syncthreads();

@@ -26,7 +26,7 @@ hipError_t launch_mfma_operands(const PointsView &P, int kind, int S, double sca
 // Per-point accumulator start, rounded-up norm and decision thresholds for one eps,
 // in working units: nu_scale = scale^2, b and e2 already in those units.
 hipError_t launch_mfma_scalars(int64_t n, const double *nu, double nu_scale, const MfmaBound &b, double e2, int d,
-                               float *cinit, float *nuup, float *U, float *V, float *Z, hipStream_t s);
+                               float *cinit, float *nuup, float *T3, hipStream_t s);
 
 // ---- greedy (greedy.hip) ----------------------------------------------------------------
 // Lists up to B uncovered ranks after the cursor and clears rowflag[0..B).
@@ -57,16 +57,23 @@ struct RangeOut {
     int32_t bn;                     // bits of the original index in a key
 };
 
+// Range-pass launchers take an optional event pair (null: none) that records
+// the dispatch's own start and end (no separate marker packets on the stream).
+struct LaunchEvents {
+    hipEvent_t start, stop;
+};
+
 hipError_t launch_range_fp32(const float *xf, const PointsView &P, double e2, Fp32Thresholds thr,
                              int refine, const int32_t *A, const int64_t *blk, int na_max,
-                             const RangeOut &o, hipStream_t s);
+                             const RangeOut &o, hipStream_t s, LaunchEvents ev = {});
 
 // One-wave check of the matrix-core layout and subnormal handling (flags, see range_mfma.hip).
 hipError_t run_selfcheck(int *flags_dev, hipStream_t s);
 // blk[0..3] = first ordinal, landmark count, rlo, settled count (see SettledSet);
 // rlo = 0 and a zero count scan every rank.
 hipError_t launch_range_mfma(const MfmaArgs &a, const PointsView &P, double e2, const int32_t *A,
-                             const int64_t *blk, int na_max, const RangeOut &o, const SettledSet &sd, hipStream_t s);
+                             const int64_t *blk, int na_max, const RangeOut &o, const SettledSet &sd, hipStream_t s,
+                             LaunchEvents ev = {});
 // Candidate-block resolve on the matrix cores: `packed` holds the candidates'
 // operands and scalars in candidate order, Pc.perm their original indices;
 // writes the conflict words (as 32-bit halves) and row flags.

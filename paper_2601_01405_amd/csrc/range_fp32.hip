@@ -6,6 +6,8 @@
 // Sec. 5.2); the host turns that bound into two thresholds so that pairs
 // outside [lo, hi) are decided for sure and the band in between is recomputed
 // with the FP64 predicate.
+#include <hip/hip_ext.h>
+
 #include "dev_common.h"
 #include "kernels.h"
 
@@ -97,12 +99,14 @@ __global__ __launch_bounds__(RF_THREADS) void k_range_fp32(const float *__restri
 }
 
 hipError_t launch_range_fp32(const float *xf, const PointsView &P, double e2, Fp32Thresholds thr, int refine,
-                             const int32_t *A, const int64_t *blk, int na_max, const RangeOut &o, hipStream_t s)
+                             const int32_t *A, const int64_t *blk, int na_max, const RangeOut &o, hipStream_t s,
+                             LaunchEvents ev)
 {
     (void)na_max;
     if (P.n <= 0) return hipSuccess;
     const int blocks = (int)((P.n + RF_THREADS - 1) / RF_THREADS);
-    k_range_fp32<<<blocks, RF_THREADS, 0, s>>>(xf, P, e2, thr, refine, A, blk, o);
+    hipExtLaunchKernelGGL(k_range_fp32, dim3(blocks), dim3(RF_THREADS), 0, s, ev.start, ev.stop, 0, xf, P, e2, thr,
+                          refine, A, blk, o);
     return hipGetLastError();
 }
 

@@ -18,6 +18,8 @@
 // compressed-distance oracle with false negatives and false positives.
 #include <cstdlib>
 
+#include <hip/hip_ext.h>
+
 #include "dev_common.h"
 #include "kernels.h"
 
@@ -136,36 +138,47 @@ __device__ __forceinline__ float to_f32_up(double v)
 }
 
 __global__ void k_mfma_scalars(int64_t n, const double *nu, double nu_scale, MfmaBound b, double e2, double g64d,
-                               float *cinit, float *nuup, float *U, float *V, float *Z)
+                               float *cinit, float *nuup, float *T3)
 {
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (r >= n) return;
+    const int64_t np = (n + 31) / 32 * 32;
+    if (r >= np) return;
+    if (r >= n) {                                      // padding of the last tile: never a member
+        T3[t3_index(r, T3_U)] = INFINITY;
+        T3[t3_index(r, T3_V)] = INFINITY;
+        T3[t3_index(r, T3_Z)] = INFINITY;
+        return;
+    }
     const double v = nu[r] * nu_scale;                 // working units (exact power-of-two scale)
     const float nf = (float)v;
     cinit[r] = -0.5f * nf;
     nuup[r] = to_f32_up(v * (1.0 + g64d) * (1.0 + 1e-12));
     const double rel = 1e-12 * (v + b.t_out + 1.0);
+    float U, V;
     if (!b.sane) {
-        U[r] = __builtin_nanf("");
-        V[r] = __builtin_nanf("");
+        U = __builtin_nanf("");
+        V = __builtin_nanf("");
     } else {
         // The kernel forms u = RN(U - w) and v = RN(V + w) with w >= alpha max|l|^2
         // widened by 2^-22; taking U and V 2^-23 further out keeps u <= U_exact - w_exact
         // and v >= V_exact + w_exact despite that rounding.
         const double u = (v - b.t_out) * 0.5 - b.beta * v - b.abs_err - rel;
         const double w = (v - b.t_in) * 0.5 + b.beta * v + b.abs_err + rel;
-        U[r] = to_f32_down(u - 0x1p-23 * fabs(u) * (1.0 + 1e-9));
-        V[r] = to_f32_up(w + 0x1p-23 * fabs(w) * (1.0 + 1e-9));
+        U = to_f32_down(u - 0x1p-23 * fabs(u) * (1.0 + 1e-9));
+        V = to_f32_up(w + 0x1p-23 * fabs(w) * (1.0 + 1e-9));
     }
-    Z[r] = (float)((v - e2) * 0.5);
+    T3[t3_index(r, T3_U)] = U;
+    T3[t3_index(r, T3_V)] = V;
+    T3[t3_index(r, T3_Z)] = (float)((v - e2) * 0.5);
 }
 
 hipError_t launch_mfma_scalars(int64_t n, const double *nu, double nu_scale, const MfmaBound &b, double e2, int d,
-                               float *cinit, float *nuup, float *U, float *V, float *Z, hipStream_t s)
+                               float *cinit, float *nuup, float *T3, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
+    const int64_t np = (n + 31) / 32 * 32;
     const double g64d = (double)d * 0x1p-53 / (1.0 - (double)d * 0x1p-53);
-    k_mfma_scalars<<<(int)((n + 255) / 256), 256, 0, s>>>(n, nu, nu_scale, b, e2, g64d, cinit, nuup, U, V, Z);
+    k_mfma_scalars<<<(int)((np + 255) / 256), 256, 0, s>>>(n, nu, nu_scale, b, e2, g64d, cinit, nuup, T3);
     return hipGetLastError();
 }
 
@@ -187,9 +200,10 @@ __device__ __forceinline__ int acc_row(int i, int half) { return 8 * (i >> 2) + 
 
 // Work split.  A workgroup of RM_WAVES waves owns RM_WAVES * RM_MP landmark
 // panels of 32 (A operands and accumulator starts in registers for the whole
-// pass) and a contiguous range of 32-point tiles.  Each tile's B operands and
-// thresholds are staged once per workgroup in LDS (double buffered: the next
-// tile's global loads are in flight while the current one is multiplied), so a
+// pass) and a contiguous range of 32-point tiles.  Tiles are staged through
+// LDS in stages of TPS tiles, double buffered, with two register sets of
+// staging loads: while stage s is multiplied, the loads of stages s+1 and s+2
+// are in flight, so memory latency has two stage-times to hide behind.  A
 // point tile is read from memory once per RM_WAVES * RM_MP * 32 landmarks.
 //
 // MEMBERS mode appends (ordinal, point) keys and sets covered bits.  CONFLICT
@@ -197,61 +211,70 @@ __device__ __forceinline__ int acc_row(int i, int half) { return 8 * (i >> 2) + 
 // packed candidate set, and the output is C32[j * stride + p] = the bits r of
 // rows i = 32 p + r < j whose ball holds candidate j, plus rowflag[j] = 1 when
 // any bit is set.
-constexpr int RM_WAVES = 8;
-constexpr int RM_THREADS = RM_WAVES * 64;
-constexpr int RM_MP = 2;
-
-// Tiles per LDS stage: the next stage's loads have TPS tiles of matrix work
-// to arrive in, and the workgroup synchronises once per stage.
-#ifndef BM_STAGE_TILES
-#define BM_STAGE_TILES 8
-#endif
-__host__ __device__ constexpr int stage_tiles(bool chunked, int ks)
-{
-    return chunked ? 1 : (ks <= 4 ? BM_STAGE_TILES : ks <= 6 ? (BM_STAGE_TILES + 1) / 2 : (BM_STAGE_TILES + 3) / 4);
-}
-// Staging vectors per thread for one stage: TPS tiles of S steps plus 96 thresholds each.
-__host__ __device__ constexpr int stage_slots(int S, int tps) { return (tps * (S * 64 + 96) + RM_THREADS - 1) / RM_THREADS; }
-
+//
 // Point space of a MEMBERS pass: tiles [0, MT) are the settled list (entries
 // < m valid), then rank tiles from rlo / 32 to the end.  A CONFLICT pass has
 // no settled part.  The grid is NGW landmark groups x `chunks` point chunks
 // (chunks a multiple of 8); the chunk length follows the device-side tile
 // count.  Workgroups are dispatched to the 8 XCDs round robin, so the NGW
 // groups of one chunk are placed on the same XCD and share its L2.
-template <int KS, bool F16, bool CONFLICT, int SLOTS, bool CHUNKED>
+constexpr int RM_WAVES = 8;
+constexpr int RM_THREADS = RM_WAVES * 64;
+constexpr int RM_MP = 2;
+
+// Tiles per LDS stage (16-32 KB of operands per stage); one tile when the
+// K steps are processed in chunks of 8.
+__host__ __device__ constexpr int stage_tiles(bool chunked, int ks)
+{
+    return chunked ? 1 : (ks <= 2 ? 16 : ks <= 4 ? 8 : ks <= 6 ? 4 : 2);
+}
+// Operand vectors of one stage, and per thread.
+__host__ __device__ constexpr int stage_vecs(bool chunked, int ks)
+{
+    return stage_tiles(chunked, ks) * (chunked ? kMaxMfmaSteps : ks) * 64;
+}
+__host__ __device__ constexpr int op_slots(bool chunked, int ks)
+{
+    return (stage_vecs(chunked, ks) + RM_THREADS - 1) / RM_THREADS;
+}
+
+template <int KS, bool F16, bool CONFLICT, bool CHUNKED>
 __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsView P, const int32_t *n_dev, double e2,
                                                            const int32_t *__restrict__ A, const int64_t *blk,
                                                            RangeOut o, SettledSet sd, uint32_t *C32, int c32_stride,
                                                            int *rowflag, int NGW, int chunks, int nch)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int S = a.S;
-    // LDS: 2 buffers of TPS tiles of [S][64] u32x4 operands, then their thresholds
     constexpr int TPS = stage_tiles(CHUNKED, KS);
-    const int buf_words = S * 64;                                  // u32x4 per tile
-    u32x4 *sB = (u32x4 *)smem;                                     // [2][TPS][S*64]
-    float *sT = (float *)(sB + 2 * TPS * buf_words);               // [2][TPS][3][32]
-    float *sC = sT + 2 * TPS * 96;                                 // [RM_WAVES*RM_MP*32] accumulator starts
-    float *sN = sC + RM_THREADS;                                   // [RM_WAVES*RM_MP*32] norm bounds
+    constexpr int OPS = op_slots(CHUNKED, KS);
+    constexpr int THV = TPS * 24;                                  // threshold vectors per stage
+    static_assert(THV <= RM_THREADS, "one threshold vector per thread");
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int S = CHUNKED ? a.S : KS;
+    const int tile_vecs = S * 64;                                  // operand vectors of one tile
+    const int buf_vecs = TPS * tile_vecs;
+    u32x4 *sB = (u32x4 *)smem;                                     // [2][TPS][S*64] operands
+    u32x4 *sT = sB + 2 * buf_vecs;                                 // [2][TPS][24]: U[32] V[32] Z[32]
+    float *sC = (float *)(sT + 2 * THV);                           // [RM_THREADS] accumulator starts
+    float *sN = sC + RM_THREADS;                                   // [RM_THREADS] norm bounds
 
     const int64_t n = n_dev ? (int64_t)*n_dev : P.n;
     const int64_t ord0 = CONFLICT ? 0 : blk[0];
     const int na = CONFLICT ? (int)n : (int)blk[1];
     const int64_t msz = CONFLICT ? 0 : blk[3];                     // settled entries
-    const int64_t MT = (msz + 31) / 32;                            // settled tiles
-    const int64_t RT0 = CONFLICT ? 0 : (blk[2] >> 5);              // first rank tile
-    const int wid = (int)(threadIdx.x >> 6), lane = lane_id(), col = lane & 31, half = lane >> 5;
+    const int MT = (int)((msz + 31) / 32);                         // settled tiles
+    const int RT0 = CONFLICT ? 0 : (int)(blk[2] >> 5);             // first rank tile
+    const int tid = (int)threadIdx.x;
+    const int wid = tid >> 6, lane = lane_id(), col = lane & 31, half = lane >> 5;
     const int xcd = (int)(blockIdx.x & 7);
     const int kk = (int)(blockIdx.x >> 3);
     const int g = kk % NGW;
-    const int64_t c = (int64_t)(kk / NGW) * 8 + xcd;
+    const int c = (kk / NGW) * 8 + xcd;
     if (g * RM_WAVES * RM_MP * 32 >= na) return;                   // workgroup-uniform
-    const int64_t NT = (n + 31) / 32;
-    const int64_t CT = MT + NT - RT0;                              // tiles of the point space
-    const int64_t tpc = (CT + chunks - 1) / chunks;
-    const int64_t t0 = c * tpc;
-    const int64_t t1 = min(CT, t0 + tpc);
+    const int NT = (int)((n + 31) / 32);
+    const int CT = MT + NT - RT0;                                  // tiles of the point space
+    const int tpc = (CT + chunks - 1) / chunks;
+    const int t0 = c * tpc;
+    const int t1 = min(CT, t0 + tpc);
     if (t0 >= t1) return;                                          // workgroup-uniform
     const int pbase = (g * RM_WAVES + wid) * RM_MP;                // first panel of this wave
     const bool live = pbase * 32 < na;                             // wave-uniform
@@ -259,15 +282,15 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
     // ---- the workgroup's landmarks: one per thread into LDS (start value, norm bound)
     static_assert(RM_WAVES * RM_MP * 32 == RM_THREADS, "one landmark per thread");
     {
-        const int aj = g * RM_THREADS + (int)threadIdx.x;
+        const int aj = g * RM_THREADS + tid;
         float cv = 0.f, nv = 0.f;
         if (aj < na) {
             const int32_t r = A ? A[aj] : aj;
             cv = a.cinit[r];
             nv = a.nuup[r];
         }
-        sC[threadIdx.x] = cv;
-        sN[threadIdx.x] = nv;
+        sC[tid] = cv;
+        sN[tid] = nv;
     }
     __syncthreads();
 
@@ -311,71 +334,69 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
     };
     if (!CHUNKED && live) load_a(0);
 
-    // ---- staging of one stage: TPS tiles x (S*64 operand vectors + 96 threshold floats)
-    const int tile_items = buf_words + 96;
-    const int items = TPS * tile_items;
-    u32x4 pre[SLOTS];
-    auto gload = [&](int64_t ts) {
+    // ---- staging.  Slot k of this thread always carries operand vector
+    // tid + k * RM_THREADS of a stage (tile op_tt[k], vector op_rem[k] of it),
+    // and thread tid < THV one threshold vector (tile th_tt, floats 4 th_q ..).
+    int op_tt[OPS], op_rem[OPS];
 #pragma unroll
-        for (int k = 0; k < SLOTS; ++k) {
-            const int it = (int)threadIdx.x + k * RM_THREADS;
-            u32x4 v = {0u, 0u, 0u, 0u};
-            if (it < items) {
-                const int tt = it / tile_items, r = it - tt * tile_items;
-                const int64_t t = ts + tt;
-                if (t < t1) {
-                    const bool settled = t < MT;
-                    const int64_t ts_ = settled ? t : RT0 + (t - MT);        // tile in its own array
-                    if (r < buf_words) {
-                        v = *(const u32x4 *)((settled ? sd.Pop : a.Pop) + ((ts_ * S) * 64 + r) * 8);
-                    } else {
-                        const int q = r - buf_words, which = q >> 5;
-                        const int64_t pt = ts_ * 32 + (q & 31);
-                        float f = INFINITY;
-                        if (settled) f = which == 0 ? sd.U[pt] : which == 1 ? sd.V[pt] : sd.Z[pt];
-                        else if (pt < n) f = which == 0 ? a.U[pt] : which == 1 ? a.V[pt] : a.Z[pt];
-                        v[0] = __float_as_uint(f);
-                    }
-                }
-            }
-            pre[k] = v;
+    for (int k = 0; k < OPS; ++k) {
+        const int it = tid + k * RM_THREADS;
+        op_tt[k] = it < buf_vecs ? it / tile_vecs : -1;
+        op_rem[k] = it - (it / tile_vecs) * tile_vecs;
+    }
+    const int th_tt = tid < THV ? tid / 24 : -1;
+    const int th_q = tid - (tid / 24) * 24;
+    u32x4 preA[OPS], preB[OPS];
+    u32x4 pretA, pretB;
+    // tile t of the point space -> its own array and the tile index in it
+    // Every load is issued (tiles past t1 and unused slots read tile t0 again,
+    // in bounds, and are never consumed), so the number of loads per stage is
+    // fixed and the waits before a store can leave the younger stage in flight.
+    auto gload = [&](int ts, u32x4 (&pre)[OPS], u32x4 &pre_t) {
+#pragma unroll
+        for (int k = 0; k < OPS; ++k) {
+            int t = ts + op_tt[k];
+            t = (op_tt[k] >= 0 && t < t1) ? t : t0;
+            const bool stl = t < MT;
+            const int64_t tl = stl ? t : t - MT + RT0;
+            const uint16_t *base = stl ? sd.Pop : a.Pop;
+            const int rem = op_tt[k] >= 0 ? op_rem[k] : 0;
+            pre[k] = *(const u32x4 *)(base + (tl * tile_vecs + rem) * 8);
+        }
+        {
+            int t = ts + th_tt;
+            t = (th_tt >= 0 && t < t1) ? t : t0;
+            const bool stl = t < MT;
+            const int64_t tl = stl ? t : t - MT + RT0;
+            const float *base = stl ? sd.T3 : a.T3;
+            pre_t = *(const u32x4 *)(base + tl * 96 + (th_tt >= 0 ? th_q : 0) * 4);
         }
     };
-    // LDS per buffer: [TPS][S*64] operand vectors, then [TPS][96] thresholds
-    auto lstore = [&](int buf) {
+    auto lstore = [&](int buf, const u32x4 (&pre)[OPS], const u32x4 &pre_t) {
 #pragma unroll
-        for (int k = 0; k < SLOTS; ++k) {
-            const int it = (int)threadIdx.x + k * RM_THREADS;
-            if (it < items) {
-                const int tt = it / tile_items, r = it - tt * tile_items;
-                if (r < buf_words) sB[(buf * TPS + tt) * buf_words + r] = pre[k];
-                else sT[(buf * TPS + tt) * 96 + (r - buf_words)] = __uint_as_float(pre[k][0]);
-            }
-        }
+        for (int k = 0; k < OPS; ++k)
+            if (op_tt[k] >= 0) sB[buf * buf_vecs + tid + k * RM_THREADS] = pre[k];
+        if (th_tt >= 0) sT[buf * THV + tid] = pre_t;
     };
 
     unsigned long long band = 0;
+    const int thr_off = a.refine ? 0 : 64;                         // screen on U (refined) or Z
     // Let the setup loads (A operands, accumulator starts) land before the loop,
     // so the only loads in flight inside it are the next stage's staging loads
     // and the waitcnt pass need not wait for them before the matrix ops.
     __builtin_amdgcn_s_waitcnt(0);
-    gload(t0);
-    for (int64_t ts = t0; ts < t1; ts += TPS) {
-        const int buf = (int)(((ts - t0) / TPS) & 1);
-        lstore(buf);
+    // One stage: store its staged loads to LDS buffer `buf`, start the loads of
+    // the stage two ahead into the same registers, multiply the stage.
+    auto run_stage = [&](int ts, int buf, u32x4 (&pre)[OPS], u32x4 &pre_t) {
+        lstore(buf, pre, pre_t);
         __syncthreads();
-        if (ts + TPS < t1) gload(ts + TPS);
-        if (!live) continue;
+        gload(ts + 2 * TPS, pre, pre_t);
+        if (!live) return;
       for (int tt = 0; tt < TPS; ++tt) {
-        const int64_t t = ts + tt;
+        const int t = ts + tt;
         if (t >= t1) break;                                             // wave-uniform
-        const int sb = (buf * TPS + tt) * buf_words;                    // this tile's operands in LDS
-        const int stt = (buf * TPS + tt) * 96;                          // and thresholds
-        const bool settled = t < MT;                                    // wave-uniform
-        const int64_t tr = settled ? t : RT0 + (t - MT);                // tile in its own array
-        const int64_t p = tr * 32 + col;                                // settled entry or rank
-        const bool pv = settled ? p < msz : p < n;
-        const float Ux = sT[stt + col], Vx = sT[stt + 32 + col], Zx = sT[stt + 64 + col];
+        const int sb = buf * buf_vecs + tt * tile_vecs;                 // this tile's operands in LDS
+        const float *thr = (const float *)(sT + buf * THV + tt * 24);   // and thresholds
         f32x16 acc[RM_MP];
         if (!CHUNKED) {
             u32x4 breg[KS];
@@ -404,18 +425,18 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
             }
         }
 
-        bool cov = false;
+        const float tcut = thr[thr_off + col];
+        bool cov = false, slow = false;
 #pragma unroll
         for (int pi = 0; pi < RM_MP; ++pi) {
             const int abase = (pbase + pi) * 32;
             if (abase >= na) break;                                      // wave-uniform
             const f32x16 av = acc[pi];
-            // u, v: conservative thresholds for this point and panel (U, V and aw carry
-            // the slack for these two roundings); +inf for padding points
-            const float u = Ux - aw[pi];
             if (!CONFLICT) {
                 // fast path: is any pair of the 32x32 tile possibly a member?
-                const float cut = a.refine ? u : Zx;
+                // u, v: conservative thresholds for this point and panel (U, V and aw
+                // carry the slack for these two roundings); +inf for padding points
+                const float cut = a.refine ? tcut - aw[pi] : tcut;
                 float m = fmaxf(fmaxf(av[0], av[1]), av[2]);
                 m = fmaxf(fmaxf(m, av[3]), av[4]);
                 m = fmaxf(fmaxf(m, av[5]), av[6]);
@@ -426,10 +447,16 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
                 m = fmaxf(m, av[15]);
                 if (!__ballot(!(m <= cut))) continue;
             }
+            slow = true;
+            const bool stl = t < MT;                                     // wave-uniform
+            const int64_t tr = stl ? t : t - MT + RT0;                   // tile in its own array
+            const int64_t p = tr * 32 + col;                             // settled entry or rank
+            const bool pv = stl ? p < msz : p < n;
             uint32_t mem = 0;
-            const int64_t xo = !pv ? 0 : settled ? (int64_t)sd.idx[p] : orig_index(P, p);
+            const int64_t xo = !pv ? 0 : stl ? (int64_t)sd.idx[p] : orig_index(P, p);
             if (a.refine) {
-                const float v = Vx + aw[pi];
+                const float u = thr[col] - aw[pi];
+                const float v = thr[32 + col] + aw[pi];
                 uint32_t bnd = 0;
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
@@ -451,10 +478,11 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
                     if (exact_member(P, orig_index(P, lr), xo, e2)) mem |= 1u << i;
                 }
             } else {
+                const float z = thr[64 + col];
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
                     const int ai = abase + acc_row(i, half);
-                    if (pv && ai < na && (!CONFLICT || ai < p) && av[i] > Zx) mem |= 1u << i;
+                    if (pv && ai < na && (!CONFLICT || ai < p) && av[i] > z) mem |= 1u << i;
                 }
             }
             if (CONFLICT) {
@@ -486,14 +514,27 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
                 ++base;
             }
         }
-        if (!CONFLICT && o.covered && !settled) {
+        if (!CONFLICT && slow && o.covered && t >= MT) {                 // wave-uniform
+            const int64_t tr = t - MT + RT0;
             const uint64_t m = __ballot(cov);
             const uint64_t bits = (m | (m >> 32)) & 0xffffffffull;
             if (bits && lane == 0)
                 atomicOr((unsigned long long *)&o.covered[(tr * 32) >> 6], (unsigned long long)(bits << ((tr * 32) & 63)));
         }
       }
+    };
+    gload(t0, preA, pretA);
+    __builtin_amdgcn_sched_barrier(0);           // issue set A before set B: the waits rely on the order
+    gload(t0 + TPS, preB, pretB);
+    // Unrolled by two (distinct registers), with the odd last stage after the
+    // loop: every path into a stage has the set it stores as the older one in flight.
+    int ts = t0;
+    while (ts + TPS < t1) {
+        run_stage(ts, 0, preA, pretA);
+        run_stage(ts + TPS, 1, preB, pretB);
+        ts += 2 * TPS;
     }
+    if (ts < t1) run_stage(ts, 0, preA, pretA);
     band = wave_sum(band);
     if (band && lane == 0 && o.st) atomicAdd(&o.st->band, band);
 }
@@ -556,10 +597,10 @@ hipError_t run_selfcheck(int *flags_dev, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int KS, bool F16, bool CONFLICT, int SLOTS, bool CHUNKED>
+template <int KS, bool F16, bool CONFLICT, bool CHUNKED>
 static hipError_t launch_ks(const MfmaArgs &a, const PointsView &P, const int32_t *n_dev, double e2, const int32_t *A,
                             const int64_t *blk, int na_max, int64_t n_max, const RangeOut &o, const SettledSet &sd,
-                            uint32_t *C32, int c32_stride, int *rowflag, int nch, hipStream_t s)
+                            uint32_t *C32, int c32_stride, int *rowflag, int nch, hipStream_t s, LaunchEvents ev)
 {
     const int npan = (na_max + 31) / 32;
     const int per_wg = RM_WAVES * RM_MP;
@@ -576,43 +617,44 @@ static hipError_t launch_ks(const MfmaArgs &a, const PointsView &P, const int32_
     chunks = (chunks + 7) / 8 * 8;                                  // whole XCD rounds
     const int64_t wgs = (int64_t)NGW * chunks;
     constexpr int TPS = stage_tiles(CHUNKED, KS);
-    const size_t shmem = (size_t)2 * TPS * (a.S * 64 * 16 + 96 * sizeof(float)) + 2 * RM_THREADS * sizeof(float);
-    k_range_mfma<KS, F16, CONFLICT, SLOTS, CHUNKED><<<(unsigned)wgs, RM_THREADS, shmem, s>>>(
-        a, P, n_dev, e2, A, blk, o, sd, C32, c32_stride, rowflag, NGW, (int)chunks, nch);
+    const size_t shmem = (size_t)2 * TPS * (a.S * 64 * 16 + 24 * 16) + 2 * RM_THREADS * sizeof(float);
+    hipExtLaunchKernelGGL(k_range_mfma<KS, F16, CONFLICT, CHUNKED>, dim3((unsigned)wgs), dim3(RM_THREADS),
+                          (uint32_t)shmem, s, ev.start, ev.stop, 0, a, P, n_dev, e2, A, blk, o, sd, C32, c32_stride,
+                          rowflag, NGW, (int)chunks, nch);
     return hipGetLastError();
 }
 
 template <bool F16, bool CONFLICT>
 static hipError_t dispatch(const MfmaArgs &a, const PointsView &P, const int32_t *n_dev, double e2, const int32_t *A,
                            const int64_t *blk, int na_max, int64_t n_max, const RangeOut &o, const SettledSet &sd,
-                           uint32_t *C32, int c32_stride, int *rowflag, hipStream_t s)
+                           uint32_t *C32, int c32_stride, int *rowflag, hipStream_t s, LaunchEvents ev)
 {
-#define BM_KS(k, nch, slots) \
-    launch_ks<k, F16, CONFLICT, slots, (nch > 1)>(a, P, n_dev, e2, A, blk, na_max, n_max, o, sd, C32, c32_stride, rowflag, \
-                                                  nch, s)
+#define BM_KS(k) \
+    launch_ks<k, F16, CONFLICT, false>(a, P, n_dev, e2, A, blk, na_max, n_max, o, sd, C32, c32_stride, rowflag, 1, s, ev)
     switch (a.S) {
-    case 1: return BM_KS(1, 1, stage_slots(1, stage_tiles(false, 1)));
-    case 2: return BM_KS(2, 1, stage_slots(2, stage_tiles(false, 2)));
-    case 3: return BM_KS(3, 1, stage_slots(3, stage_tiles(false, 3)));
-    case 4: return BM_KS(4, 1, stage_slots(4, stage_tiles(false, 4)));
-    case 5: return BM_KS(5, 1, stage_slots(5, stage_tiles(false, 5)));
-    case 6: return BM_KS(6, 1, stage_slots(6, stage_tiles(false, 6)));
-    case 7: return BM_KS(7, 1, stage_slots(7, stage_tiles(false, 7)));
-    case 8: return BM_KS(8, 1, stage_slots(8, stage_tiles(false, 8)));
-    default: return launch_ks<8, F16, CONFLICT, stage_slots(kMaxMfmaSteps, stage_tiles(true, 8)), true>(
-                 a, P, n_dev, e2, A, blk, na_max, n_max, o, sd, C32, c32_stride, rowflag, (a.S + 7) / 8, s);
+    case 1: return BM_KS(1);
+    case 2: return BM_KS(2);
+    case 3: return BM_KS(3);
+    case 4: return BM_KS(4);
+    case 5: return BM_KS(5);
+    case 6: return BM_KS(6);
+    case 7: return BM_KS(7);
+    case 8: return BM_KS(8);
+    default: return launch_ks<8, F16, CONFLICT, true>(a, P, n_dev, e2, A, blk, na_max, n_max, o, sd, C32, c32_stride,
+                                                      rowflag, (a.S + 7) / 8, s, ev);
     }
 #undef BM_KS
 }
 
 hipError_t launch_range_mfma(const MfmaArgs &a, const PointsView &P, double e2, const int32_t *A,
-                             const int64_t *blk, int na_max, const RangeOut &o, const SettledSet &sd, hipStream_t s)
+                             const int64_t *blk, int na_max, const RangeOut &o, const SettledSet &sd, hipStream_t s,
+                             LaunchEvents ev)
 {
     if (a.S > kMaxMfmaSteps) return hipErrorInvalidValue;
     if (P.n <= 0 || na_max <= 0) return hipSuccess;
     if (a.kind == MFMA_F16)
-        return dispatch<true, false>(a, P, nullptr, e2, A, blk, na_max, P.n, o, sd, nullptr, 0, nullptr, s);
-    return dispatch<false, false>(a, P, nullptr, e2, A, blk, na_max, P.n, o, sd, nullptr, 0, nullptr, s);
+        return dispatch<true, false>(a, P, nullptr, e2, A, blk, na_max, P.n, o, sd, nullptr, 0, nullptr, s, ev);
+    return dispatch<false, false>(a, P, nullptr, e2, A, blk, na_max, P.n, o, sd, nullptr, 0, nullptr, s, ev);
 }
 
 hipError_t launch_resolve_mfma(const MfmaArgs &packed, const PointsView &Pc, const int32_t *nc_dev, double e2, int B,
@@ -623,8 +665,8 @@ hipError_t launch_resolve_mfma(const MfmaArgs &packed, const PointsView &Pc, con
     const SettledSet none{};
     const int stride = 2 * ((B + 63) / 64);
     if (packed.kind == MFMA_F16)
-        return dispatch<true, true>(packed, Pc, nc_dev, e2, nullptr, nullptr, B, B, o, none, C32, stride, rowflag, s);
-    return dispatch<false, true>(packed, Pc, nc_dev, e2, nullptr, nullptr, B, B, o, none, C32, stride, rowflag, s);
+        return dispatch<true, true>(packed, Pc, nc_dev, e2, nullptr, nullptr, B, B, o, none, C32, stride, rowflag, s, {});
+    return dispatch<false, true>(packed, Pc, nc_dev, e2, nullptr, nullptr, B, B, o, none, C32, stride, rowflag, s, {});
 }
 
 // Copy the gathered candidates' operands and scalars into a packed set
@@ -660,9 +702,8 @@ __global__ void k_pack_candidates(MfmaArgs a, const int32_t *cand, const GreedyS
             const int32_t r = v ? cand[j] : 0;
             ((float *)out.cinit)[j] = v ? a.cinit[r] : 0.f;
             ((float *)out.nuup)[j] = v ? a.nuup[r] : 0.f;
-            ((float *)out.U)[j] = v ? a.U[r] : INFINITY;
-            ((float *)out.V)[j] = v ? a.V[r] : INFINITY;
-            ((float *)out.Z)[j] = v ? a.Z[r] : INFINITY;
+#pragma unroll
+            for (int w = 0; w < 3; ++w) ((float *)out.T3)[t3_index(j, w)] = v ? a.T3[t3_index(r, w)] : INFINITY;
             cand_orig[j] = v ? (perm ? perm[r] : r) : 0;
         }
     }
