@@ -250,6 +250,7 @@ def main():
     graph_ms = {f"eps={eps}": float(np.median([run[i][0]["ms_total"] for run in runs]))
                 for i, eps in enumerate(eps_list)}
     range_ms = sum(s["ms_range_kernel"] for run in runs for s, _, _ in run)
+    range_ev_ms = sum(s["ms_range_events"] for run in runs for s, _, _ in run)
     launches = sum(s["range_launches"] for run in runs for s, _, _ in run)
     range_pairs = sum(s["range_pairs"] for run in runs for s, _, _ in run)
     log(f"refined {used_path}: {value:.1f} G pair-dists/s, {elapsed / args.steps * 1e3:.2f} ms/step, "
@@ -284,8 +285,14 @@ def main():
     roofline = {"bound": "mfma", "kernel": "k_range_mfma", "achieved": achieved, "peak": peak,
                 "unit": "TFLOP/s", "frac": (achieved / peak) if achieved else None,
                 "traffic": read_traffic(range_pairs / max(launches, 1)),
-                "per_launch_ms": range_ms / max(launches, 1), "launches_per_step": launches / args.steps,
-                "flops_per_pair": 2 * d}
+                "per_launch_ms": range_ms / max(launches, 1),
+                "per_launch_ms_events": range_ev_ms / max(launches, 1),
+                "launches_per_step": launches / args.steps,
+                "flops_per_pair": 2 * d, "pairs_per_launch": range_pairs / max(launches, 1),
+                "timing": "per_launch_ms: execution window of each range-pass launch on the device clock "
+                          "(first wave start to last wave end), summed over the timed steps; "
+                          "per_launch_ms_events: HIP events on the library stream around the same launches, "
+                          "which also hold each dispatch's wait behind the previous kernel"}
 
     # -- the FP64 oracle on the host, a bounded sample of the same workload
     cpu = None

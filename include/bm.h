@@ -109,11 +109,16 @@ typedef struct {
     int64_t candidates;           /* candidates gathered over all blocks                       */
     int32_t path;                 /* path actually used                                        */
     int32_t block;                /* block size actually used                                  */
-    double  ms_range_kernel;      /* summed durations of the range-pass launches (profile = 1) */
+    double  ms_range_kernel;      /* summed execution windows of the range-pass launches, first
+                                     wave start to last wave end on the device clock
+                                     (profile = 1)                                             */
     int64_t range_launches;       /* range-pass launches                                       */
     int64_t range_pairs;          /* landmark-point pairs they evaluated; below pairs_useful
                                      on the refined matrix-core paths, which skip earlier
                                      landmarks (never in a later landmark's ball)             */
+    double  ms_range_events;      /* summed HIP-event intervals around the same launches on the
+                                     library's stream (profile = 1); each also holds the
+                                     dispatch's wait behind the previous kernel               */
 } bm_stats;
 
 typedef struct {

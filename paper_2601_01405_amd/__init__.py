@@ -48,7 +48,8 @@ class Stats(ctypes.Structure):
                 ("pairs_useful", ctypes.c_int64), ("pairs_issued", ctypes.c_int64),
                 ("band_pairs", ctypes.c_int64), ("blocks", ctypes.c_int64), ("candidates", ctypes.c_int64),
                 ("path", ctypes.c_int32), ("block", ctypes.c_int32), ("ms_range_kernel", ctypes.c_double),
-                ("range_launches", ctypes.c_int64), ("range_pairs", ctypes.c_int64)]
+                ("range_launches", ctypes.c_int64), ("range_pairs", ctypes.c_int64),
+                ("ms_range_events", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}

@@ -394,6 +394,15 @@ bm_result *run_job(const Job &job, const bm_options &o)
             }
         } ev_guard{evs};
         SettledSet sd{};
+        // device-clock execution windows of the range passes (profile = 1)
+        KernelClock *kclk = nullptr;
+        if (o.profile) {
+            kclk = dev.alloc<KernelClock>(1);
+            const KernelClock init{~0ull, 0ull, 0ull};
+            std::memcpy(dev.pinned, &init, sizeof init);
+            hip_ok(hipMemcpyAsync(kclk, dev.pinned, sizeof init, hipMemcpyHostToDevice, dev.s), "clock init");
+            dev.sync();
+        }
         auto run_range = [&](const int32_t *Alist, const int64_t *blk, uint64_t *covered) {
             ro.keys = keys;
             ro.cap = cap;
@@ -404,7 +413,7 @@ bm_result *run_job(const Job &job, const bm_options &o)
                 hip_ok(hipEventCreate(&e1), "hipEventCreate");
                 evs.emplace_back(e0, e1);
             }
-            const LaunchEvents ev{e0, e1};     // the dispatch's own start and end
+            const LaunchEvents ev{e0, e1, kclk};
             if (path == BM_PATH_FP32)
                 hip_ok(launch_range_fp32(xf, P, e2, thr32, o.refine, Alist, blk, B, ro, dev.s, ev), "range_fp32");
             else
@@ -556,7 +565,13 @@ bm_result *run_job(const Job &job, const bm_options &o)
         for (auto &e : evs) {
             float ms = 0.f;
             hip_ok(hipEventElapsedTime(&ms, e.first, e.second), "hipEventElapsedTime");
-            res->stats.ms_range_kernel += ms;
+            res->stats.ms_range_events += ms;
+        }
+        if (kclk) {
+            const KernelClock kc = dev.fetch(kclk);
+            int khz = 0;
+            hip_ok(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev.dev), "wall clock rate");
+            if (khz > 0) res->stats.ms_range_kernel = (double)kc.ticks / (double)khz;
         }
         res->stats.band_pairs = (int64_t)hs.band;
         res->stats.pairs_useful = L * n;

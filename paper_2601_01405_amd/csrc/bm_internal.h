@@ -82,6 +82,13 @@ inline size_t mfma_operand_words(int64_t points, int S)
     return (size_t)((points + 31) / 32) * (size_t)S * 64 * 8;
 }
 
+// Execution window of a kernel on the device clock: every workgroup lowers
+// `start` at entry; the last one to finish adds (now - start) to `ticks` and
+// resets `start` and `done` for the next launch.
+struct KernelClock {
+    unsigned long long start, done, ticks;
+};
+
 enum { T3_U = 0, T3_V = 1, T3_Z = 2 };
 __host__ __device__ inline int64_t t3_index(int64_t r, int which) { return (r >> 5) * 96 + which * 32 + (r & 31); }
 // floats of a tiled threshold array for `points` points

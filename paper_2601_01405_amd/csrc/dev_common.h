@@ -69,6 +69,26 @@ __device__ __forceinline__ bool exact_member(const PointsView &P, int64_t a, int
     return exact_member_t<2>(P.X, P.d, a, b, e2);
 }
 
+// ---- kernel execution window (see KernelClock) ------------------------------------------
+__device__ __forceinline__ void clock_enter(KernelClock *clk)
+{
+    if (clk && threadIdx.x == 0) atomicMin(&clk->start, (unsigned long long)wall_clock64());
+}
+// Called by every workgroup once all its threads are done (after a barrier).
+__device__ __forceinline__ void clock_leave(KernelClock *clk)
+{
+    if (!clk || threadIdx.x != 0) return;
+    __threadfence();
+    const unsigned long long prev = atomicAdd(&clk->done, 1ull);
+    if (prev == (unsigned long long)gridDim.x * gridDim.y * gridDim.z - 1ull) {
+        const unsigned long long st = atomicAdd(&clk->start, 0ull);
+        const unsigned long long now = (unsigned long long)wall_clock64();
+        atomicAdd(&clk->ticks, now - st);
+        atomicExch(&clk->start, ~0ull);
+        atomicExch(&clk->done, 0ull);
+    }
+}
+
 // ---- wave64 helpers ------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 

@@ -61,6 +61,7 @@ struct RangeOut {
 // the dispatch's own start and end (no separate marker packets on the stream).
 struct LaunchEvents {
     hipEvent_t start, stop;
+    KernelClock *clock;             // device-clock execution window (may be null)
 };
 
 hipError_t launch_range_fp32(const float *xf, const PointsView &P, double e2, Fp32Thresholds thr,

@@ -20,8 +20,9 @@ constexpr int RF_KC = 32;      // coordinates per chunk
 __global__ __launch_bounds__(RF_THREADS) void k_range_fp32(const float *__restrict__ xf, PointsView P, double e2,
                                                            Fp32Thresholds thr, int refine,
                                                            const int32_t *__restrict__ A,
-                                                           const int64_t *blk, RangeOut o)
+                                                           const int64_t *blk, RangeOut o, KernelClock *clk)
 {
+    clock_enter(clk);
     __shared__ float lt[RF_LT][RF_KC];
     __shared__ int32_t lrank[RF_LT];
     const int64_t ord0 = blk[0];
@@ -96,6 +97,10 @@ __global__ __launch_bounds__(RF_THREADS) void k_range_fp32(const float *__restri
     }
     band = wave_sum(band);
     if (band && lane_id() == 0) atomicAdd(&o.st->band, band);
+    if (clk) {
+        __syncthreads();
+        clock_leave(clk);
+    }
 }
 
 hipError_t launch_range_fp32(const float *xf, const PointsView &P, double e2, Fp32Thresholds thr, int refine,
@@ -106,7 +111,7 @@ hipError_t launch_range_fp32(const float *xf, const PointsView &P, double e2, Fp
     if (P.n <= 0) return hipSuccess;
     const int blocks = (int)((P.n + RF_THREADS - 1) / RF_THREADS);
     hipExtLaunchKernelGGL(k_range_fp32, dim3(blocks), dim3(RF_THREADS), 0, s, ev.start, ev.stop, 0, xf, P, e2, thr,
-                          refine, A, blk, o);
+                          refine, A, blk, o, ev.clock);
     return hipGetLastError();
 }
 

@@ -242,8 +242,10 @@ template <int KS, bool F16, bool CONFLICT, bool CHUNKED>
 __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsView P, const int32_t *n_dev, double e2,
                                                            const int32_t *__restrict__ A, const int64_t *blk,
                                                            RangeOut o, SettledSet sd, uint32_t *C32, int c32_stride,
-                                                           int *rowflag, int NGW, int chunks, int nch)
+                                                           int *rowflag, int NGW, int chunks, int nch,
+                                                           KernelClock *clk)
 {
+    clock_enter(clk);
     constexpr int TPS = stage_tiles(CHUNKED, KS);
     constexpr int OPS = op_slots(CHUNKED, KS);
     constexpr int THV = TPS * 24;                                  // threshold vectors per stage
@@ -269,13 +271,19 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
     const int kk = (int)(blockIdx.x >> 3);
     const int g = kk % NGW;
     const int c = (kk / NGW) * 8 + xcd;
-    if (g * RM_WAVES * RM_MP * 32 >= na) return;                   // workgroup-uniform
+    if (g * RM_WAVES * RM_MP * 32 >= na) {                         // workgroup-uniform
+        clock_leave(clk);
+        return;
+    }
     const int NT = (int)((n + 31) / 32);
     const int CT = MT + NT - RT0;                                  // tiles of the point space
     const int tpc = (CT + chunks - 1) / chunks;
     const int t0 = c * tpc;
     const int t1 = min(CT, t0 + tpc);
-    if (t0 >= t1) return;                                          // workgroup-uniform
+    if (t0 >= t1) {                                                // workgroup-uniform
+        clock_leave(clk);
+        return;
+    }
     const int pbase = (g * RM_WAVES + wid) * RM_MP;                // first panel of this wave
     const bool live = pbase * 32 < na;                             // wave-uniform
 
@@ -537,6 +545,10 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
     if (ts < t1) run_stage(ts, 0, preA, pretA);
     band = wave_sum(band);
     if (band && lane == 0 && o.st) atomicAdd(&o.st->band, band);
+    if (clk) {
+        __syncthreads();
+        clock_leave(clk);
+    }
 }
 
 // ---- self-check of the matrix-core behaviour the error bound relies on -------------------
@@ -620,7 +632,7 @@ static hipError_t launch_ks(const MfmaArgs &a, const PointsView &P, const int32_
     const size_t shmem = (size_t)2 * TPS * (a.S * 64 * 16 + 24 * 16) + 2 * RM_THREADS * sizeof(float);
     hipExtLaunchKernelGGL(k_range_mfma<KS, F16, CONFLICT, CHUNKED>, dim3((unsigned)wgs), dim3(RM_THREADS),
                           (uint32_t)shmem, s, ev.start, ev.stop, 0, a, P, n_dev, e2, A, blk, o, sd, C32, c32_stride,
-                          rowflag, NGW, (int)chunks, nch);
+                          rowflag, NGW, (int)chunks, nch, ev.clock);
     return hipGetLastError();
 }
 
