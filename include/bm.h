@@ -91,8 +91,12 @@ typedef struct {
     int64_t max_device_bytes;     /* 0 = unlimited; else BM_ENOMEM beyond this many bytes      */
     int64_t init_member_capacity; /* 0 = automatic; a small value exercises buffer regrowth    */
     void   *stream;               /* hipStream_t to run on; NULL = a library-owned stream      */
-    int32_t profile;              /* 1: time every range-pass launch with HIP events on `stream` */
-    int32_t reserved;             /* must be 0                                                 */
+    int32_t profile;              /* 1: time the range passes: device-clock execution windows,
+                                     plus HIP events on `stream` around each directly launched
+                                     pass (not around passes replayed from a graph)           */
+    int32_t no_graph;             /* 0: past its first few blocks the greedy replays a captured
+                                     HIP graph of the per-block kernels; 1: every kernel is
+                                     launched directly                                        */
 } bm_options;
 
 typedef struct {

@@ -39,7 +39,7 @@ class Options(ctypes.Structure):
                 ("device", ctypes.c_int32), ("points_on_device", ctypes.c_int32),
                 ("results_on_device", ctypes.c_int32), ("max_device_bytes", ctypes.c_int64),
                 ("init_member_capacity", ctypes.c_int64), ("stream", ctypes.c_void_p),
-                ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("no_graph", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -240,7 +240,7 @@ def _points(points):
 
 
 def options(path="auto", refine=True, block=0, device=-1, results_on_device=False, max_device_bytes=0,
-            init_member_capacity=0, stream=None, points_on_device=0, profile=False) -> Options:
+            init_member_capacity=0, stream=None, points_on_device=0, profile=False, graph=True) -> Options:
     o = Options()
     _check(load_library().bm_default_options(ctypes.byref(o)))
     o.path = PATHS[path] if isinstance(path, str) else int(path)
@@ -253,6 +253,7 @@ def options(path="auto", refine=True, block=0, device=-1, results_on_device=Fals
     o.init_member_capacity = int(init_member_capacity)
     o.stream = stream
     o.profile = 1 if profile else 0
+    o.no_graph = 0 if graph else 1
     return o
 
 

@@ -49,6 +49,11 @@ size_t dtype_size(int32_t dtype) { return dtype == BM_F64 ? 8 : dtype == BM_F32 
 int bitlen(uint64_t v) { return v ? 64 - __builtin_clzll(v) : 0; }
 
 // ---- device context: selected device, stream, tracked allocations ------------------------
+constexpr size_t kPinnedBytes = 64 * 1024;
+constexpr size_t kUploadStage = kPinnedBytes - 4096;
+constexpr int kUploadBlocks = 64;                   // blocks per table of directly launched passes
+static_assert(kUploadBlocks * 32 <= 2048, "block table staging");
+static_assert(kUploadBlocks * sizeof(RangeTask) <= kUploadStage, "task staging");
 struct Device {
     int dev = 0, prev_dev = -1;
     hipStream_t s = nullptr;
@@ -72,7 +77,7 @@ struct Device {
             hip_ok(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
             own_stream = true;
         }
-        hip_ok(hipHostMalloc(&pinned, 4096, hipHostMallocDefault), "hipHostMalloc");
+        hip_ok(hipHostMalloc(&pinned, kPinnedBytes, hipHostMallocDefault), "hipHostMalloc");
     }
     ~Device()
     {
@@ -127,13 +132,27 @@ struct Device {
             }
     }
     void sync() { hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"); }
+    // Pinned host memory: [0, 4 KB) staging of small reads and block tables,
+    // [4 KB, kPinnedBytes) staging of uploads.  Both wait for their copy.
     template <class T> T fetch(const T *dptr)
     {
-        hip_ok(hipMemcpyAsync(pinned, dptr, sizeof(T), hipMemcpyDeviceToHost, s), "hipMemcpyAsync D2H");
+        static_assert(sizeof(T) <= 2048, "fetch staging");
+        hip_ok(hipMemcpyAsync((char *)pinned + 2048, dptr, sizeof(T), hipMemcpyDeviceToHost, s), "hipMemcpyAsync D2H");
         sync();
         T v;
-        std::memcpy(&v, pinned, sizeof(T));
+        std::memcpy(&v, (char *)pinned + 2048, sizeof(T));
         return v;
+    }
+    void upload(void *dptr, const void *src, size_t bytes)
+    {
+        for (size_t off = 0; off < bytes; off += kUploadStage) {
+            const size_t m = std::min(kUploadStage, bytes - off);
+            sync();                                     // the staging area is free again
+            std::memcpy((char *)pinned + 4096, (const char *)src + off, m);
+            hip_ok(hipMemcpyAsync((char *)dptr + off, (char *)pinned + 4096, m, hipMemcpyHostToDevice, s),
+                   "hipMemcpyAsync H2D");
+        }
+        sync();
     }
 };
 
@@ -151,7 +170,8 @@ void check_common(const void *points, int64_t n, int32_t d, int32_t dtype, doubl
     if (o.refine != 0 && o.refine != 1) fail(BM_EINVAL, "refine must be 0 or 1");
     if (o.block < 0 || o.block > 4096) fail(BM_EINVAL, "block must be 0 (automatic) or 1..4096");
     if (o.max_device_bytes < 0 || o.init_member_capacity < 0) fail(BM_EINVAL, "negative size option");
-    if ((o.profile != 0 && o.profile != 1) || o.reserved != 0) fail(BM_EINVAL, "bad profile/reserved option");
+    if ((o.profile != 0 && o.profile != 1) || (o.no_graph != 0 && o.no_graph != 1))
+        fail(BM_EINVAL, "profile and no_graph must be 0 or 1");
 }
 
 bool host_all_finite(const void *points, int64_t count, int32_t dtype)
@@ -186,6 +206,61 @@ std::vector<int32_t> check_order(const int64_t *order, int64_t n)
     }
     return perm;
 }
+
+struct Pair64 {
+    unsigned long long v[2];
+};
+
+int64_t range_target_wg()
+{
+    // about one workgroup per compute unit (256) unless BM_RANGE_WORKGROUPS says otherwise
+    static const int64_t env_wg = [] {
+        const char *e = getenv("BM_RANGE_WORKGROUPS");
+        return e ? atoll(e) : 0LL;
+    }();
+    return env_wg > 0 ? env_wg : 256;
+}
+
+// A captured sequence of kernels replayed as one HIP graph.  Captured on a
+// private stream (the caller's may be the legacy default stream, which cannot
+// be captured), launched on any stream.  No memset nodes are captured: the
+// block kernels clear what they need themselves.
+struct GraphRunner {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    hipStream_t cs = nullptr;
+    bool ready() const { return x != nullptr; }
+    void reset()
+    {
+        if (x) (void)hipGraphExecDestroy(x);
+        if (g) (void)hipGraphDestroy(g);
+        x = nullptr;
+        g = nullptr;
+    }
+    template <class F> void capture(F &&enqueue)
+    {
+        reset();
+        if (!cs) hip_ok(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
+        hip_ok(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+        try {
+            enqueue(cs);
+        } catch (...) {
+            hipGraph_t dead = nullptr;
+            (void)hipStreamEndCapture(cs, &dead);
+            if (dead) (void)hipGraphDestroy(dead);
+            throw;
+        }
+        hip_ok(hipStreamEndCapture(cs, &g), "end capture");
+        hip_ok(hipGraphInstantiate(&x, g, nullptr, nullptr, 0), "graph instantiate");
+    }
+    void launch(hipStream_t s) { hip_ok(hipGraphLaunch(x, s), "graph launch"); }
+    ~GraphRunner()
+    {
+        reset();
+        if (cs) (void)hipStreamDestroy(cs);
+    }
+};
+constexpr int kGraphBlocks = 8;                     // greedy blocks per captured graph
 
 bm_result *new_result()
 {
@@ -239,7 +314,7 @@ int auto_block(int64_t n, int path)
         if (n >= (1 << 13)) return 256;
         return 64;
     }
-    if (n >= (1 << 17)) return 2048;
+    if (n >= (1 << 17)) return 4096;
     if (n >= (1 << 13)) return 256;
     return 64;
 }
@@ -310,10 +385,10 @@ bm_result *run_job(const Job &job, const bm_options &o)
             nu = dev.alloc<double>((size_t)n);
             unsigned long long *st2 = dev.zeros<unsigned long long>(2);
             hip_ok(launch_point_stats(P, nu, st2, dev.s), "point_stats");
-            hip_ok(hipMemcpyAsync(dev.pinned, st2, 16, hipMemcpyDeviceToHost, dev.s), "stats D2H");
-            dev.sync();
             unsigned long long raw[2];
-            std::memcpy(raw, dev.pinned, 16);
+            const auto st2h = dev.fetch((const Pair64 *)st2);
+            raw[0] = st2h.v[0];
+            raw[1] = st2h.v[1];
             std::memcpy(&max_nu, &raw[0], 8);
             std::memcpy(&max_abs, &raw[1], 8);
         }
@@ -376,10 +451,17 @@ bm_result *run_job(const Job &job, const bm_options &o)
         int32_t *lm_d = dev.alloc<int32_t>((size_t)lm_cap);
         int32_t *lm_rank = job.fixed ? lm_d : dev.alloc<int32_t>((size_t)lm_cap);   // fixed mode: ranks = indices
         int32_t *A = dev.alloc<int32_t>((size_t)B);
-        int64_t *fixtab = dev.alloc<int64_t>(4 * 64);              // up to 64 rows of blk[0..3]
+        int64_t *fixtab = dev.alloc<int64_t>(4 * kUploadBlocks);   // blk[0..3] rows of directly launched passes
+        // device task tables: [0] the greedy's range pass, [1] its resolve,
+        // [2 + q] directly launched passes of the fixed-landmark / recompute paths
+        RangeTask *rtask = dev.alloc<RangeTask>(2 + kUploadBlocks);
+        ChainTask *ctask = dev.alloc<ChainTask>(1);
         GreedyState hs{};
         int64_t L = 0;
-        RangeOut ro{nullptr, keys, cap, st, bn};
+        RangeOut ro{nullptr, keys, cap, &st->nkeys, st, 0, bn};
+        int32_t NGW = 1, chunks = 8;
+        const bool mfma = path != BM_PATH_FP32;
+        if (mfma) range_grid(B, n, range_target_wg(), &NGW, &chunks);
 
         // range-pass launches, optionally bracketed by events on the same stream
         std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
@@ -399,32 +481,77 @@ bm_result *run_job(const Job &job, const bm_options &o)
         if (o.profile) {
             kclk = dev.alloc<KernelClock>(1);
             const KernelClock init{~0ull, 0ull, 0ull};
-            std::memcpy(dev.pinned, &init, sizeof init);
-            hip_ok(hipMemcpyAsync(kclk, dev.pinned, sizeof init, hipMemcpyHostToDevice, dev.s), "clock init");
-            dev.sync();
+            dev.upload(kclk, &init, sizeof init);
         }
-        auto run_range = [&](const int32_t *Alist, const int64_t *blk, uint64_t *covered) {
-            ro.keys = keys;
-            ro.cap = cap;
-            ro.covered = covered;
+        auto range_task = [&](const int32_t *Alist, const int64_t *blk, uint64_t *covered) {
+            RangeTask t{};
+            t.a = ma;
+            t.P = P;
+            t.n_dev = nullptr;
+            t.e2 = e2;
+            t.A = Alist;
+            t.blk = blk;
+            t.o = ro;
+            t.o.keys = keys;
+            t.o.cap = cap;
+            t.o.covered = covered;
+            t.sd = sd;
+            t.NGW = NGW;
+            t.chunks = chunks;
+            t.wg0 = 0;
+            return t;
+        };
+        // A range pass on stream `s` (task: its device-side descriptor, matrix-core
+        // path); per-launch events only for direct launches (profile = 1).
+        auto run_range_on = [&](hipStream_t s, bool events, const RangeTask *task, const int32_t *Alist,
+                                const int64_t *blk, uint64_t *covered) {
             hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (o.profile) {
+            if (events && o.profile) {
                 hip_ok(hipEventCreate(&e0), "hipEventCreate");
                 hip_ok(hipEventCreate(&e1), "hipEventCreate");
                 evs.emplace_back(e0, e1);
             }
             const LaunchEvents ev{e0, e1, kclk};
-            if (path == BM_PATH_FP32)
-                hip_ok(launch_range_fp32(xf, P, e2, thr32, o.refine, Alist, blk, B, ro, dev.s, ev), "range_fp32");
-            else
-                hip_ok(launch_range_mfma(ma, P, e2, Alist, blk, B, ro, sd, dev.s, ev), "range_mfma");
-            res->stats.range_launches++;
+            if (!mfma) {
+                RangeOut r = ro;
+                r.keys = keys;
+                r.cap = cap;
+                r.covered = covered;
+                hip_ok(launch_range_fp32(xf, P, e2, thr32, o.refine, Alist, blk, B, r, s, ev), "range_fp32");
+            } else {
+                hip_ok(launch_range_tasks(task, nullptr, (int64_t)NGW * chunks, ma.kind, ma.S, false, s, ev),
+                       "range_mfma");
+            }
+        };
+        // Directly launched passes over rows of blocks (L0, na, rlo, m): the
+        // fixed-landmark mode and the recompute after a key-buffer overflow.
+        int64_t *tab_h = (int64_t *)dev.pinned;       // [0, 2 KB) of the pinned staging
+        auto run_rows = [&](const std::vector<BlockLog> &rows, const int32_t *lm_list) {
+            for (size_t j = 0; j < rows.size(); j += kUploadBlocks) {
+                const size_t m = std::min<size_t>(kUploadBlocks, rows.size() - j);
+                dev.sync();
+                for (size_t q = 0; q < m; ++q) {
+                    tab_h[4 * q] = rows[j + q].L0;
+                    tab_h[4 * q + 1] = rows[j + q].na;
+                    tab_h[4 * q + 2] = rows[j + q].rlo;
+                    tab_h[4 * q + 3] = rows[j + q].m;
+                }
+                hip_ok(hipMemcpyAsync(fixtab, tab_h, m * 32, hipMemcpyHostToDevice, dev.s), "upload table");
+                if (mfma) {
+                    std::vector<RangeTask> tv(m);
+                    for (size_t q = 0; q < m; ++q) tv[q] = range_task(lm_list + rows[j + q].L0, fixtab + 4 * q, nullptr);
+                    dev.upload(rtask + 2, tv.data(), m * sizeof(RangeTask));
+                }
+                for (size_t q = 0; q < m; ++q) {
+                    run_range_on(dev.s, true, rtask + 2 + q, lm_list + rows[j + q].L0, fixtab + 4 * q, nullptr);
+                    res->stats.range_launches++;
+                }
+            }
         };
         // The key buffer overflowed: grow it, then recompute the memberships of
         // the landmark ranges [L0_j, L0_j + na_j) from the first incomplete one on,
         // restarting the key counter where that block began.  The landmark set is
         // unaffected (covered bits do not depend on the key buffer).
-        int64_t *tab_h = (int64_t *)((char *)dev.pinned + 2048);
         auto refill = [&](const std::vector<BlockLog> &logs) {
             const unsigned long long need = hs.nkeys;
             const unsigned long long start = logs.front().nkeys_before;
@@ -435,20 +562,8 @@ bm_result *run_job(const Job &job, const bm_options &o)
             dev.release(keys);
             keys = nk;
             cap = ncap;
-            std::memcpy(dev.pinned, &start, 8);
-            hip_ok(hipMemcpyAsync(&st->nkeys, dev.pinned, 8, hipMemcpyHostToDevice, dev.s), "reset nkeys");
-            for (size_t j = 0; j < logs.size(); j += 64) {
-                const size_t m = std::min<size_t>(64, logs.size() - j);
-                dev.sync();
-                for (size_t q = 0; q < m; ++q) {
-                    tab_h[4 * q] = logs[j + q].L0;
-                    tab_h[4 * q + 1] = logs[j + q].na;
-                    tab_h[4 * q + 2] = logs[j + q].rlo;
-                    tab_h[4 * q + 3] = logs[j + q].m;
-                }
-                hip_ok(hipMemcpyAsync(fixtab, tab_h, m * 32, hipMemcpyHostToDevice, dev.s), "upload table");
-                for (size_t q = 0; q < m; ++q) run_range(lm_rank + logs[j + q].L0, fixtab + 4 * q, nullptr);
-            }
+            dev.upload(&st->nkeys, &start, 8);
+            run_rows(logs, lm_rank);
             const GreedyState chk = dev.fetch(st);
             if (chk.nkeys != need) fail(BM_EINTERNAL, "membership count changed on recompute");
             hs.nkeys = chk.nkeys;
@@ -460,18 +575,7 @@ bm_result *run_job(const Job &job, const bm_options &o)
             if (L > 0) hip_ok(hipMemcpyAsync(lm_d, job.fixed, (size_t)L * 4, hipMemcpyHostToDevice, dev.s), "upload lm");
             std::vector<BlockLog> all;      // every rank scanned: rlo = 0, no settled list
             for (int64_t a0 = 0; a0 < L; a0 += B) all.push_back(BlockLog{a0, std::min<int64_t>(B, L - a0), 0, 0, 0});
-            for (size_t j = 0; j < all.size(); j += 64) {
-                const size_t m = std::min<size_t>(64, all.size() - j);
-                dev.sync();
-                for (size_t q = 0; q < m; ++q) {
-                    tab_h[4 * q] = all[j + q].L0;
-                    tab_h[4 * q + 1] = all[j + q].na;
-                    tab_h[4 * q + 2] = 0;
-                    tab_h[4 * q + 3] = 0;
-                }
-                hip_ok(hipMemcpyAsync(fixtab, tab_h, m * 32, hipMemcpyHostToDevice, dev.s), "upload table");
-                for (size_t q = 0; q < m; ++q) run_range(lm_d + all[j + q].L0, fixtab + 4 * q, nullptr);
-            }
+            run_rows(all, lm_d);
             hs = dev.fetch(st);
             if (hs.nkeys > cap) refill(all);    // all[0].nkeys_before = 0: recompute everything
             res->stats.blocks = (int64_t)all.size();
@@ -483,26 +587,10 @@ bm_result *run_job(const Job &job, const bm_options &o)
             int32_t *cand = dev.alloc<int32_t>((size_t)B);
             uint64_t *C = dev.alloc<uint64_t>((size_t)B * nw);
             int *rowflag = dev.alloc<int>((size_t)B);
-            // packed candidate set for the matrix-core resolve
-            MfmaArgs pk = ma;
-            int32_t *cand_orig = nullptr;
-            const bool mfma_resolve = path != BM_PATH_FP32;
-            if (mfma_resolve) {
-                const int64_t Bp = (B + 31) / 32 * 32;
-                const size_t words = mfma_operand_words(Bp, ma.S);
-                pk.Pop = dev.alloc<uint16_t>(words);
-                pk.Qop = (ma.Qop != ma.Pop) ? dev.alloc<uint16_t>(words) : pk.Pop;
-                float *psc = dev.alloc<float>((size_t)Bp * 2 + t3_floats(Bp));
-                pk.cinit = psc;
-                pk.nuup = psc + Bp;
-                pk.T3 = psc + 2 * Bp;
-                cand_orig = dev.alloc<int32_t>((size_t)Bp);
-            }
-            const PointsView Pc{Xd, B, d, job.dtype, cand_orig};
             // Settled list (refined matrix-core path): landmarks are skipped as
             // points of later range passes, since no landmark is in another's ball.
             // The unrefined predicate is not symmetric, so there every rank is scanned.
-            const bool settle = mfma_resolve && o.refine;
+            const bool settle = mfma && o.refine;
             uint64_t *islm = nullptr;
             if (settle) {
                 islm = dev.zeros<uint64_t>((size_t)((n + 63) / 64));
@@ -515,31 +603,102 @@ bm_result *run_job(const Job &job, const bm_options &o)
             }
             BlockLog *blog = dev.alloc<BlockLog>(kBlockLogSize);
             std::vector<BlockLog> blog_h(kBlockLogSize);
+            // the chain's descriptor and its two matrix-core tasks
+            ChainTask ct{};
+            ct.covered = covered;
+            ct.n = n;
+            ct.st = st;
+            ct.B = B;
+            ct.settle = settle ? 1 : 0;
+            ct.cand = cand;
+            ct.rowflag = rowflag;
+            ct.islm = islm;
+            ct.a = ma;
+            ct.sd = sd;
+            ct.perm = perm_d;
+            ct.C = C;
+            ct.A = A;
+            ct.landmarks = lm_d;
+            ct.lm_rank = lm_rank;
+            ct.blog = blog;
+            ct.nkeys = &st->nkeys;
+            ct.ndone = nullptr;
+            dev.upload(ctask, &ct, sizeof ct);
+            // [0]: the greedy's range pass, whose last workgroup opens the next block;
+            // [1]: the candidate resolve, whose last workgroup accepts.
+            int32_t rNGW = 1, rchunks = 8;
+            if (mfma) range_grid(B, B, range_target_wg(), &rNGW, &rchunks);
+            auto upload_tasks = [&]() {
+                RangeTask t[2];
+                t[0] = range_task(A, &st->L0, covered);
+                t[0].chain = ctask;
+                t[1] = RangeTask{};
+                t[1].a = ma;
+                t[1].P = P;
+                t[1].n_dev = &st->nc;
+                t[1].e2 = e2;
+                t[1].A = cand;
+                t[1].o = RangeOut{nullptr, nullptr, 0, &st->nkeys, st, 0, 0};
+                t[1].C32 = (uint32_t *)C;
+                t[1].c32_stride = 2 * nw;
+                t[1].rowflag = rowflag;
+                t[1].NGW = rNGW;
+                t[1].chunks = rchunks;
+                t[1].chain = ctask;
+                dev.upload(rtask, t, sizeof t);
+            };
+            upload_tasks();
+            const int64_t res_wgs = (int64_t)rNGW * rchunks;
+            // One block of the greedy on stream s.  Matrix-core paths: resolve
+            // (+ accept) and range pass (+ open the next block), after a first
+            // open before the loop.  FP32 path: open, exact resolve, accept, range.
+            auto enqueue_block = [&](hipStream_t s, bool events) {
+                if (mfma) {
+                    hip_ok(launch_range_tasks(rtask + 1, nullptr, res_wgs, ma.kind, ma.S, true, s), "resolve_mfma");
+                    run_range_on(s, events, rtask, A, &st->L0, covered);
+                    return;
+                }
+                hip_ok(launch_block_begin(ctask, 1, s), "block begin");
+                hip_ok(launch_resolve_exact(P, e2, cand, st, B, C, rowflag, s), "resolve");
+                hip_ok(launch_accept(ctask, 1, B, s), "accept");
+                run_range_on(s, events, rtask, A, &st->L0, covered);
+            };
+            if (mfma) hip_ok(launch_block_begin(ctask, 1, dev.s), "first block");
+            // Past the first batch, blocks are replayed from a captured HIP graph of
+            // kGraphBlocks blocks (every kernel reads its block from the device-side
+            // state, so one graph serves every block; blocks after the last one find
+            // no candidate and do nothing).  The FP32 pass takes its key buffer by
+            // value, so a graph of that path is captured again when the buffer moves.
+            GraphRunner gr;
+            const bool use_graph = !o.no_graph;
             // Blocks are queued back to back; the host looks at the state once per batch.
             int batch = 4;
+            bool direct_batch = true;
+            void *graph_keys = nullptr;
             for (;;) {
-                const unsigned long long blocks_before = hs.blocks;
-                for (int k = 0; k < batch; ++k) {
-                    hip_ok(launch_gather(covered, n, st, B, cand, rowflag, dev.s), "gather");
-                    if (settle) hip_ok(launch_settle(islm, st, cand, ma, sd, perm_d, dev.s), "settle");
-                    if (mfma_resolve) {
-                        hip_ok(launch_pack_candidates(ma, cand, st, perm_d, B, pk, cand_orig, dev.s), "pack");
-                        hip_ok(launch_resolve_mfma(pk, Pc, &st->nc, e2, B, (uint32_t *)C, rowflag, st, dev.s),
-                               "resolve_mfma");
-                    } else {
-                        hip_ok(launch_resolve_exact(P, e2, cand, st, B, C, rowflag, dev.s), "resolve");
+                const unsigned long long blocks_before = hs.accepted;
+                if (use_graph && !direct_batch) {
+                    if (!gr.ready() || (!mfma && graph_keys != (void *)keys)) {
+                        gr.capture([&](hipStream_t cs) {
+                            for (int k = 0; k < kGraphBlocks; ++k) enqueue_block(cs, false);
+                        });
+                        graph_keys = keys;
                     }
-                    hip_ok(launch_accept(C, rowflag, cand, st, B, A, lm_d, lm_rank, blog, perm_d, islm, n, dev.s),
-                           "accept");
-                    run_range(A, &st->L0, covered);
+                    for (int k = 0; k < batch; k += kGraphBlocks) gr.launch(dev.s);
+                } else {
+                    for (int k = 0; k < batch; ++k) enqueue_block(dev.s, true);
                 }
+                res->stats.range_launches += batch;
+                direct_batch = false;
                 hs = dev.fetch(st);
                 if (hs.error) fail(BM_EINTERNAL, "candidate acceptance did not converge");
                 if (hs.nkeys > cap) {
                     hip_ok(hipMemcpy(blog_h.data(), blog, sizeof(BlockLog) * kBlockLogSize, hipMemcpyDeviceToHost),
                            "read block log");
                     std::vector<BlockLog> logs;
-                    for (unsigned long long b = blocks_before; b < hs.blocks; ++b)
+                    // blocks accepted in this batch (a block opened by the batch's last
+                    // range pass is not accepted yet: its keys come in the next batch)
+                    for (unsigned long long b = blocks_before; b < hs.accepted; ++b)
                         logs.push_back(blog_h[b % kBlockLogSize]);
                     // first block whose keys did not all fit
                     size_t first = 0;
@@ -551,9 +710,10 @@ bm_result *run_job(const Job &job, const bm_options &o)
                     }
                     if (first == logs.size()) fail(BM_EINTERNAL, "overflow not attributed to a block");
                     refill(std::vector<BlockLog>(logs.begin() + (long)first, logs.end()));
+                    upload_tasks();                 // the greedy's pass writes to the new buffer
                 }
                 if (hs.done) break;
-                batch = std::min(batch * 2, 64);
+                batch = std::min(batch * 2, 64);     // 8, 16, 32, 64: whole graphs
             }
             L = hs.L;
             res->stats.blocks = (int64_t)hs.blocks;

@@ -36,6 +36,9 @@ struct GreedyState {
     unsigned long long candidates;  // candidates over all blocks
     unsigned long long resolve_pairs;
     unsigned long long range_pairs; // landmark-point pairs the range passes computed
+    unsigned long long accepted;    // blocks accepted (their block log entries are written)
+    unsigned int ticket;            // workgroups of the running launch that have finished
+    unsigned int pad2_;
 };
 
 // Per-block record for recomputing a block's memberships after the key
@@ -117,6 +120,64 @@ struct MfmaArgs {
     int32_t S;                      // K / 16
     int32_t kind;
     int32_t refine;
+};
+
+// Where a range pass puts its members: key (ordinal << bn | original index) | tag
+// at position atomicAdd(nkeys, 1) when it is below cap (the count goes on past
+// cap, so an overflow is seen and the block recomputed into a bigger buffer).
+struct RangeOut {
+    uint64_t *covered;              // rank-order bitmap, may be null (fixed-landmark mode)
+    uint64_t *keys;
+    unsigned long long cap;
+    unsigned long long *nkeys;      // key counter (one per build, or shared by a batch)
+    GreedyState *st;                // band counter
+    uint64_t tag;                   // or-ed into every key: the chain number in a batch, else 0
+    int32_t bn;                     // bits of the original index in a key
+};
+
+// One greedy chain (one point cloud at one radius), as the block-opening and
+// acceptance kernels see it; a launch of those kernels runs one workgroup per chain.
+struct ChainTask {
+    const uint64_t *covered;        // rank-order covered bitmap
+    int64_t n;
+    GreedyState *st;
+    int32_t B;                      // candidate block size
+    int32_t settle;                 // 1: keep the settled non-landmark list (refined matrix-core path)
+    int32_t *cand;                  // [B] candidate ranks
+    int32_t *rowflag;               // [B]
+    uint64_t *islm;                 // rank-order landmark bitmap (settle)
+    MfmaArgs a;                     // the chain's operands and scalars
+    SettledSet sd;
+    const int32_t *perm;            // rank -> original index (null: identity)
+    const uint64_t *C;              // conflict words, ceil(B/64) per candidate
+    int32_t *A;                     // accepted ranks of the block
+    int32_t *landmarks;             // original indices, selection order
+    int32_t *lm_rank;               // ranks, selection order
+    BlockLog *blog;
+    const unsigned long long *nkeys;   // the key counter its range passes append to
+    unsigned long long *ndone;      // chains finished (batch), or null
+};
+
+// One matrix-core range pass (or candidate-block resolve) of a launch.  A launch
+// serves one or more tasks of the same operand kind and K: workgroup b works for
+// task task_of[b] (task 0 without a map) as its local workgroup b - wg0.
+struct RangeTask {
+    MfmaArgs a;
+    PointsView P;                   // resolve: the candidates (perm = their original indices)
+    const int32_t *n_dev;           // device-side point count (resolve: candidate count), or null
+    double e2;
+    const int32_t *A;               // landmark ranks; null: 0, 1, 2, ... (resolve)
+    const int64_t *blk;             // blk[0..3]: first ordinal, count, rlo, settled count (see SettledSet)
+    RangeOut o;
+    SettledSet sd;
+    uint32_t *C32;                  // resolve output: conflict words, row flags
+    int32_t c32_stride;
+    int32_t *rowflag;
+    int32_t NGW, chunks;            // this task's grid: NGW landmark groups x chunks point chunks
+    int32_t wg0;                    // its first workgroup in the launch (a multiple of 8)
+    const ChainTask *chain;         // if set, the task's last workgroup to finish runs the chain's
+                                    // next serial step: accept after a resolve, open the next
+                                    // block after a range pass
 };
 
 } // namespace bm

@@ -75,10 +75,10 @@ __device__ __forceinline__ void clock_enter(KernelClock *clk)
     if (clk && threadIdx.x == 0) atomicMin(&clk->start, (unsigned long long)wall_clock64());
 }
 // Called by every workgroup once all its threads are done (after a barrier).
+// Only atomics touch the clock, so no fence is needed.
 __device__ __forceinline__ void clock_leave(KernelClock *clk)
 {
     if (!clk || threadIdx.x != 0) return;
-    __threadfence();
     const unsigned long long prev = atomicAdd(&clk->done, 1ull);
     if (prev == (unsigned long long)gridDim.x * gridDim.y * gridDim.z - 1ull) {
         const unsigned long long st = atomicAdd(&clk->start, 0ull);

@@ -29,34 +29,21 @@ hipError_t launch_mfma_scalars(int64_t n, const double *nu, double nu_scale, con
                                float *cinit, float *nuup, float *T3, hipStream_t s);
 
 // ---- greedy (greedy.hip) ----------------------------------------------------------------
-// Lists up to B uncovered ranks after the cursor and clears rowflag[0..B).
-hipError_t launch_gather(const uint64_t *covered, int64_t n, GreedyState *st, int B, int32_t *cand,
-                         int *rowflag, hipStream_t s);
+// Opens a block of every chain (one workgroup each): lists up to B uncovered
+// ranks after the cursor and clears rowflag[0..B); with `settle` appends the
+// settled non-landmarks below the first candidate to the chain's settled set;
+// with `pack` packs the candidates' operands and scalars for the matrix-core
+// resolve.  A chain whose gather finds nothing is done (counted in *ndone).
+hipError_t launch_block_begin(const ChainTask *chains, int nchains, hipStream_t s);
 // Conflict words of the candidate block with the FP64 predicate on every pair.
 hipError_t launch_resolve_exact(const PointsView &P, double e2, const int32_t *cand, const GreedyState *st,
                                 int B, uint64_t *C, int *rowflag, hipStream_t s);
-// Accepts in rank order; appends to landmarks (original indices) and lm_rank
-// at ordinal st->L, and records the block in blog[st->blocks % kBlockLogSize].
-hipError_t launch_accept(const uint64_t *C, const int *rowflag, const int32_t *cand, GreedyState *st, int B,
-                         int32_t *A, int32_t *landmarks, int32_t *lm_rank, BlockLog *blog, const int32_t *perm,
-                         uint64_t *islm, int64_t n, hipStream_t s);
-// After a gather: append the settled non-landmarks below the block's first candidate.
-hipError_t launch_settle(const uint64_t *islm, GreedyState *st, const int32_t *cand, const MfmaArgs &a,
-                         const SettledSet &out, const int32_t *perm, hipStream_t s);
+// Accepts in rank order (one workgroup per chain); appends to landmarks
+// (original indices) and lm_rank at ordinal st->L, and records the block in
+// blog[(st->blocks - 1) % kBlockLogSize].
+hipError_t launch_accept(const ChainTask *chains, int nchains, int maxB, hipStream_t s);
 
 // ---- range passes -----------------------------------------------------------------------
-// Range pass of landmarks A[0..blk[1]) (ranks) with ordinals blk[0] + i;
-// blk points to device memory (the greedy state's L0/na, or a fixed table).
-// Members are appended as keys (ordinal << bn | original index) and their
-// covered bits set.
-struct RangeOut {
-    uint64_t *covered;              // rank-order bitmap, may be null (fixed-landmark mode)
-    uint64_t *keys;
-    unsigned long long cap;
-    GreedyState *st;                // nkeys / band counters
-    int32_t bn;                     // bits of the original index in a key
-};
-
 // Range-pass launchers take an optional event pair (null: none) that records
 // the dispatch's own start and end (no separate marker packets on the stream).
 struct LaunchEvents {
@@ -64,24 +51,22 @@ struct LaunchEvents {
     KernelClock *clock;             // device-clock execution window (may be null)
 };
 
+// Plain FP32 range pass of landmarks A[0..blk[1]) (ranks), ordinals blk[0] + i.
 hipError_t launch_range_fp32(const float *xf, const PointsView &P, double e2, Fp32Thresholds thr,
                              int refine, const int32_t *A, const int64_t *blk, int na_max,
                              const RangeOut &o, hipStream_t s, LaunchEvents ev = {});
 
 // One-wave check of the matrix-core layout and subnormal handling (flags, see range_mfma.hip).
 hipError_t run_selfcheck(int *flags_dev, hipStream_t s);
-// blk[0..3] = first ordinal, landmark count, rlo, settled count (see SettledSet);
-// rlo = 0 and a zero count scan every rank.
-hipError_t launch_range_mfma(const MfmaArgs &a, const PointsView &P, double e2, const int32_t *A,
-                             const int64_t *blk, int na_max, const RangeOut &o, const SettledSet &sd, hipStream_t s,
-                             LaunchEvents ev = {});
-// Candidate-block resolve on the matrix cores: `packed` holds the candidates'
-// operands and scalars in candidate order, Pc.perm their original indices;
-// writes the conflict words (as 32-bit halves) and row flags.
-hipError_t launch_resolve_mfma(const MfmaArgs &packed, const PointsView &Pc, const int32_t *nc_dev, double e2, int B,
-                               uint32_t *C32, int *rowflag, GreedyState *st, hipStream_t s);
-hipError_t launch_pack_candidates(const MfmaArgs &a, const int32_t *cand, const GreedyState *st, const int32_t *perm,
-                                  int B, const MfmaArgs &out, int32_t *cand_orig, hipStream_t s);
+// Grid of one matrix-core range task: landmark groups and point chunks (a
+// multiple of 8) for up to na_max landmarks against up to n_max points, about
+// target_wg workgroups.
+void range_grid(int na_max, int64_t n_max, int64_t target_wg, int32_t *NGW, int32_t *chunks);
+// Matrix-core range passes (conflict = false) or candidate resolves (true) of
+// tasks that share operand kind and K = 16 S, in one launch of total_wgs
+// workgroups (task_of maps workgroups to tasks; null: one task).
+hipError_t launch_range_tasks(const RangeTask *tasks, const int32_t *task_of, int64_t total_wgs, int kind, int S,
+                              bool conflict, hipStream_t s, LaunchEvents ev = {});
 
 // ---- membership CSR (csr.hip) -------------------------------------------------------------
 hipError_t sort_keys(void *tmp, size_t *tmp_bytes, const uint64_t *in, uint64_t *out, size_t count,

@@ -84,10 +84,10 @@ __global__ __launch_bounds__(RF_THREADS) void k_range_fp32(const float *__restri
                     mem = exact_member(P, orig_index(P, lrank[l]), xo, e2);
                 }
             }
-            const unsigned long long pos = wave_append(&o.st->nkeys, mem);
+            const unsigned long long pos = wave_append(o.nkeys, mem);
             if (mem) {
                 cov = true;
-                if (pos < o.cap) o.keys[pos] = ((uint64_t)(ord0 + a0 + l) << o.bn) | (uint64_t)xo;
+                if (pos < o.cap) o.keys[pos] = ((uint64_t)(ord0 + a0 + l) << o.bn) | (uint64_t)xo | o.tag;
             }
         }
     }
@@ -110,8 +110,11 @@ hipError_t launch_range_fp32(const float *xf, const PointsView &P, double e2, Fp
     (void)na_max;
     if (P.n <= 0) return hipSuccess;
     const int blocks = (int)((P.n + RF_THREADS - 1) / RF_THREADS);
-    hipExtLaunchKernelGGL(k_range_fp32, dim3(blocks), dim3(RF_THREADS), 0, s, ev.start, ev.stop, 0, xf, P, e2, thr,
-                          refine, A, blk, o, ev.clock);
+    if (ev.start || ev.stop)          // events attached to the dispatch (not capturable in a graph)
+        hipExtLaunchKernelGGL(k_range_fp32, dim3(blocks), dim3(RF_THREADS), 0, s, ev.start, ev.stop, 0, xf, P, e2,
+                              thr, refine, A, blk, o, ev.clock);
+    else
+        k_range_fp32<<<dim3(blocks), dim3(RF_THREADS), 0, s>>>(xf, P, e2, thr, refine, A, blk, o, ev.clock);
     return hipGetLastError();
 }
 

@@ -16,11 +16,13 @@
 // is decided by the FP64 predicate (the verified range set of Sec. 5.3).
 // With refine = 0 the pair is a member iff G > Z_x = (|x|^2 - e2)/2: a
 // compressed-distance oracle with false negatives and false positives.
+#include <algorithm>
 #include <cstdlib>
 
 #include <hip/hip_ext.h>
 
 #include "dev_common.h"
+#include "greedy_dev.h"
 #include "kernels.h"
 
 namespace bm {
@@ -207,10 +209,10 @@ __device__ __forceinline__ int acc_row(int i, int half) { return 8 * (i >> 2) + 
 // point tile is read from memory once per RM_WAVES * RM_MP * 32 landmarks.
 //
 // MEMBERS mode appends (ordinal, point) keys and sets covered bits.  CONFLICT
-// mode is the candidate-block resolve: landmarks and points are the same
-// packed candidate set, and the output is C32[j * stride + p] = the bits r of
-// rows i = 32 p + r < j whose ball holds candidate j, plus rowflag[j] = 1 when
-// any bit is set.
+// mode is the candidate-block resolve: landmarks and points are both the
+// block's candidates (rank A[j] for candidate j, read in place), and the
+// output is C32[j * stride + p] = the bits r of rows i = 32 p + r < j whose
+// ball holds candidate j, plus rowflag[j] = 1 when any bit is set.
 //
 // Point space of a MEMBERS pass: tiles [0, MT) are the settled list (entries
 // < m valid), then rank tiles from rlo / 32 to the end.  A CONFLICT pass has
@@ -238,11 +240,51 @@ __host__ __device__ constexpr int op_slots(bool chunked, int ks)
     return (stage_vecs(chunked, ks) + RM_THREADS - 1) / RM_THREADS;
 }
 
+// Workgroup exit: the execution-clock window, then, for a task with a chain
+// step, a ticket; the task's last workgroup to finish runs the chain's next
+// serial step (accept after a resolve, open the next block after a range
+// pass).  No workgroup waits for another.
+template <bool CONFLICT>
+__device__ void range_wg_exit(const RangeTask &T, KernelClock *clk, unsigned char *smem)
+{
+    __syncthreads();                                               // every wave's stores have reached L2
+    clock_leave(clk);
+    const ChainTask *chain = T.chain;
+    if (!chain) return;                                            // workgroup-uniform
+    __shared__ int sh_last;
+    if (threadIdx.x == 0) {
+        GreedyState *st = chain->st;
+        // One agent-scope release per workgroup (it writes back this XCD's L2,
+        // which holds the whole workgroup's stores), one acquire in the last.
+        const unsigned int tk = __hip_atomic_fetch_add(&st->ticket, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const bool last = tk + 1u == (unsigned int)T.NGW * (unsigned int)T.chunks;
+        if (last) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");     // every workgroup's writes are visible
+            st->ticket = 0u;                                       // for the chain's next launch
+        }
+        sh_last = last ? 1 : 0;
+    }
+    __syncthreads();                                               // (the acquire invalidated the CU's caches)
+    if (!sh_last) return;
+    if (CONFLICT) block_accept<RM_THREADS>(*chain, smem);
+    else block_open<RM_THREADS>(*chain, smem);
+}
+
+// LDS of a range workgroup: the double-buffered stages, the accumulator
+// starts and norm bounds, then one band queue of kQueue entries per wave.
+constexpr int kQueue = 512;
+__host__ __device__ constexpr size_t queue_offset(int S, int TPS)
+{
+    return (size_t)2 * TPS * (S * 64 * 16 + 24 * 16) + 2 * RM_THREADS * sizeof(float);
+}
+__host__ __device__ constexpr size_t range_lds_bytes(int S, int TPS)
+{
+    return queue_offset(S, TPS) + (size_t)RM_WAVES * kQueue * 8;
+}
+
 template <int KS, bool F16, bool CONFLICT, bool CHUNKED>
-__global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsView P, const int32_t *n_dev, double e2,
-                                                           const int32_t *__restrict__ A, const int64_t *blk,
-                                                           RangeOut o, SettledSet sd, uint32_t *C32, int c32_stride,
-                                                           int *rowflag, int NGW, int chunks, int nch,
+__global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__restrict__ tasks,
+                                                           const int32_t *__restrict__ task_of, int nch,
                                                            KernelClock *clk)
 {
     clock_enter(clk);
@@ -251,6 +293,14 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
     constexpr int THV = TPS * 24;                                  // threshold vectors per stage
     static_assert(THV <= RM_THREADS, "one threshold vector per thread");
     extern __shared__ __align__(16) unsigned char smem[];
+    const RangeTask &T = tasks[task_of ? task_of[blockIdx.x] : 0];
+    const MfmaArgs a = T.a;
+    const PointsView P = T.P;
+    const double e2 = T.e2;
+    const int32_t *__restrict__ A = T.A;
+    const RangeOut o = T.o;
+    const SettledSet sd = T.sd;
+    const int NGW = T.NGW, chunks = T.chunks;
     const int S = CHUNKED ? a.S : KS;
     const int tile_vecs = S * 64;                                  // operand vectors of one tile
     const int buf_vecs = TPS * tile_vecs;
@@ -259,7 +309,8 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
     float *sC = (float *)(sT + 2 * THV);                           // [RM_THREADS] accumulator starts
     float *sN = sC + RM_THREADS;                                   // [RM_THREADS] norm bounds
 
-    const int64_t n = n_dev ? (int64_t)*n_dev : P.n;
+    const int64_t n = T.n_dev ? (int64_t)*T.n_dev : P.n;
+    const int64_t *blk = T.blk;
     const int64_t ord0 = CONFLICT ? 0 : blk[0];
     const int na = CONFLICT ? (int)n : (int)blk[1];
     const int64_t msz = CONFLICT ? 0 : blk[3];                     // settled entries
@@ -267,12 +318,13 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
     const int RT0 = CONFLICT ? 0 : (int)(blk[2] >> 5);             // first rank tile
     const int tid = (int)threadIdx.x;
     const int wid = tid >> 6, lane = lane_id(), col = lane & 31, half = lane >> 5;
-    const int xcd = (int)(blockIdx.x & 7);
-    const int kk = (int)(blockIdx.x >> 3);
+    const int lb = (int)blockIdx.x - T.wg0;                        // workgroup within the task
+    const int xcd = lb & 7;
+    const int kk = lb >> 3;
     const int g = kk % NGW;
     const int c = (kk / NGW) * 8 + xcd;
     if (g * RM_WAVES * RM_MP * 32 >= na) {                         // workgroup-uniform
-        clock_leave(clk);
+        range_wg_exit<CONFLICT>(T, clk, smem);
         return;
     }
     const int NT = (int)((n + 31) / 32);
@@ -281,7 +333,7 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
     const int t0 = c * tpc;
     const int t1 = min(CT, t0 + tpc);
     if (t0 >= t1) {                                                // workgroup-uniform
-        clock_leave(clk);
+        range_wg_exit<CONFLICT>(T, clk, smem);
         return;
     }
     const int pbase = (g * RM_WAVES + wid) * RM_MP;                // first panel of this wave
@@ -360,24 +412,43 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
     // Every load is issued (tiles past t1 and unused slots read tile t0 again,
     // in bounds, and are never consumed), so the number of loads per stage is
     // fixed and the waits before a store can leave the younger stage in flight.
+    // A resolve reads its candidates in place: candidate j is rank A[j] (slots
+    // past the count repeat the last candidate and are masked out later).
     auto gload = [&](int ts, u32x4 (&pre)[OPS], u32x4 &pre_t) {
 #pragma unroll
         for (int k = 0; k < OPS; ++k) {
             int t = ts + op_tt[k];
             t = (op_tt[k] >= 0 && t < t1) ? t : t0;
-            const bool stl = t < MT;
-            const int64_t tl = stl ? t : t - MT + RT0;
-            const uint16_t *base = stl ? sd.Pop : a.Pop;
             const int rem = op_tt[k] >= 0 ? op_rem[k] : 0;
-            pre[k] = *(const u32x4 *)(base + (tl * tile_vecs + rem) * 8);
+            if (CONFLICT) {
+                const int sl = rem >> 6, ln = rem & 63;                 // step and lane of the vector
+                const int64_t r = A[min((int64_t)t * 32 + (ln & 31), n - 1)];
+                pre[k] = *(const u32x4 *)(a.Pop + ((((r >> 5) * S + sl) * 64) + (r & 31) + 32 * (ln >> 5)) * 8);
+            } else {
+                const bool stl = t < MT;
+                const int64_t tl = stl ? t : t - MT + RT0;
+                const uint16_t *base = stl ? sd.Pop : a.Pop;
+                pre[k] = *(const u32x4 *)(base + (tl * tile_vecs + rem) * 8);
+            }
         }
         {
             int t = ts + th_tt;
             t = (th_tt >= 0 && t < t1) ? t : t0;
-            const bool stl = t < MT;
-            const int64_t tl = stl ? t : t - MT + RT0;
-            const float *base = stl ? sd.T3 : a.T3;
-            pre_t = *(const u32x4 *)(base + tl * 96 + (th_tt >= 0 ? th_q : 0) * 4);
+            const int q = th_tt >= 0 ? th_q : 0;
+            if (CONFLICT) {                                             // U, V or Z of four candidates
+                const int which = q >> 3, p0 = 4 * (q & 7);
+                float v[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    v[e] = a.T3[t3_index(A[min((int64_t)t * 32 + p0 + e, n - 1)], which)];
+                pre_t = u32x4{__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
+                              __float_as_uint(v[3])};
+            } else {
+                const bool stl = t < MT;
+                const int64_t tl = stl ? t : t - MT + RT0;
+                const float *base = stl ? sd.T3 : a.T3;
+                pre_t = *(const u32x4 *)(base + tl * 96 + q * 4);
+            }
         }
     };
     auto lstore = [&](int buf, const u32x4 (&pre)[OPS], const u32x4 &pre_t) {
@@ -389,6 +460,40 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
 
     unsigned long long band = 0;
     const int thr_off = a.refine ? 0 : 64;                         // screen on U (refined) or Z
+
+    // Band queue of this wave (refined range pass): band pairs wait in LDS and
+    // are rechecked after the loop, 64 at a time, one per lane, so that their
+    // row loads overlap instead of stalling the wave once per pair (a full
+    // queue rechecks in place).  Entry: landmark index in the pass << 40 |
+    // settled flag << 32 | point (rank or settled entry).
+    uint64_t *bq = (uint64_t *)(smem + queue_offset(CHUNKED ? a.S : KS, TPS)) + wid * kQueue;
+    int qn = 0;                                                    // wave-uniform
+    auto flush_queue = [&]() {
+        for (int q0 = 0; q0 < qn; q0 += 64) {
+            const bool have = q0 + lane < qn;
+            const uint64_t e = have ? bq[q0 + lane] : 0ull;
+            const int ai = (int)(e >> 40);
+            const bool stl = (e >> 32) & 1ull;
+            const int64_t p = (int64_t)(uint32_t)e;
+            bool memb = false;
+            int64_t xo = 0;
+            if (have) {
+                xo = stl ? (int64_t)sd.idx[p] : orig_index(P, p);
+                const int32_t lr = A ? A[ai] : ai;
+                memb = exact_member(P, orig_index(P, lr), xo, e2);
+            }
+            const uint64_t bal = __ballot(memb);
+            if (!bal) continue;
+            unsigned long long kb = 0;
+            if (lane == 0) kb = atomicAdd(o.nkeys, (unsigned long long)__popcll(bal));
+            kb = __shfl(kb, 0, 64) + (unsigned long long)mbcnt(bal);
+            if (memb) {
+                if (kb < o.cap) o.keys[kb] = ((uint64_t)(ord0 + ai) << o.bn) | (uint64_t)xo | o.tag;
+                if (!stl && o.covered) atomicOr((unsigned long long *)&o.covered[p >> 6], 1ull << (p & 63));
+            }
+        }
+        qn = 0;
+    };
     // Let the setup loads (A operands, accumulator starts) land before the loop,
     // so the only loads in flight inside it are the next stage's staging loads
     // and the waitcnt pass need not wait for them before the matrix ops.
@@ -461,7 +566,7 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
             const int64_t p = tr * 32 + col;                             // settled entry or rank
             const bool pv = stl ? p < msz : p < n;
             uint32_t mem = 0;
-            const int64_t xo = !pv ? 0 : stl ? (int64_t)sd.idx[p] : orig_index(P, p);
+            const int64_t xo = !pv ? 0 : CONFLICT ? orig_index(P, A[p]) : stl ? (int64_t)sd.idx[p] : orig_index(P, p);
             if (a.refine) {
                 const float u = thr[col] - aw[pi];
                 const float v = thr[32 + col] + aw[pi];
@@ -477,13 +582,30 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
                         else bnd |= 1u << i;
                     }
                 }
-                while (bnd) {
-                    const int i = __builtin_ctz(bnd);
-                    bnd &= bnd - 1;
-                    ++band;
-                    const int ai = abase + acc_row(i, half);
-                    const int32_t lr = A ? A[ai] : ai;
-                    if (exact_member(P, orig_index(P, lr), xo, e2)) mem |= 1u << i;
+                const int bc = __popc(bnd);
+                band += (unsigned long long)bc;
+                const int bincl = wave_incl_scan(bc);
+                const int btot = __shfl(bincl, 63, 64);
+                if (!CONFLICT && btot > 0 && qn + btot <= kQueue) {
+                    // queue them (rechecked after the loop, lane-parallel)
+                    int pos = qn + bincl - bc;
+                    while (bnd) {
+                        const int i = __builtin_ctz(bnd);
+                        bnd &= bnd - 1;
+                        const int ai = abase + acc_row(i, half);
+                        bq[pos++] = ((uint64_t)ai << 40) | ((uint64_t)(stl ? 1 : 0) << 32) | (uint64_t)(uint32_t)p;
+                    }
+                    qn += btot;
+                    __builtin_amdgcn_wave_barrier();
+                } else {
+                    // the queue is full (or a resolve): recheck in place
+                    while (bnd) {
+                        const int i = __builtin_ctz(bnd);
+                        bnd &= bnd - 1;
+                        const int ai = abase + acc_row(i, half);
+                        const int32_t lr = A ? A[ai] : ai;
+                        if (exact_member(P, orig_index(P, lr), xo, e2)) mem |= 1u << i;
+                    }
                 }
             } else {
                 const float z = thr[64 + col];
@@ -500,8 +622,8 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
                     if ((mem >> i) & 1u) w |= 1u << acc_row(i, half);
                 w |= __shfl_xor(w, 32, 64);
                 if (half == 0 && pv) {
-                    C32[p * c32_stride + (pbase + pi)] = w;
-                    if (w) rowflag[p] = 1;
+                    T.C32[p * T.c32_stride + (pbase + pi)] = w;
+                    if (w) T.rowflag[p] = 1;
                 }
                 continue;
             }
@@ -511,14 +633,14 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
             const int incl = wave_incl_scan(cnt);
             const int total = __shfl(incl, 63, 64);
             unsigned long long base = 0;
-            if (lane == 0) base = atomicAdd(&o.st->nkeys, (unsigned long long)total);
+            if (lane == 0) base = atomicAdd(o.nkeys, (unsigned long long)total);
             base = __shfl(base, 0, 64) + (unsigned long long)(incl - cnt);
             cov |= cnt != 0;
             while (mem) {
                 const int i = __builtin_ctz(mem);
                 mem &= mem - 1;
                 if (base < o.cap)
-                    o.keys[base] = ((uint64_t)(ord0 + abase + acc_row(i, half)) << o.bn) | (uint64_t)xo;
+                    o.keys[base] = ((uint64_t)(ord0 + abase + acc_row(i, half)) << o.bn) | (uint64_t)xo | o.tag;
                 ++base;
             }
         }
@@ -543,12 +665,10 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(MfmaArgs a, PointsVie
         ts += 2 * TPS;
     }
     if (ts < t1) run_stage(ts, 0, preA, pretA);
+    if (!CONFLICT && live) flush_queue();
     band = wave_sum(band);
     if (band && lane == 0 && o.st) atomicAdd(&o.st->band, band);
-    if (clk) {
-        __syncthreads();
-        clock_leave(clk);
-    }
+    range_wg_exit<CONFLICT>(T, clk, smem);
 }
 
 // ---- self-check of the matrix-core behaviour the error bound relies on -------------------
@@ -609,41 +729,41 @@ hipError_t run_selfcheck(int *flags_dev, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int KS, bool F16, bool CONFLICT, bool CHUNKED>
-static hipError_t launch_ks(const MfmaArgs &a, const PointsView &P, const int32_t *n_dev, double e2, const int32_t *A,
-                            const int64_t *blk, int na_max, int64_t n_max, const RangeOut &o, const SettledSet &sd,
-                            uint32_t *C32, int c32_stride, int *rowflag, int nch, hipStream_t s, LaunchEvents ev)
+void range_grid(int na_max, int64_t n_max, int64_t target_wg, int32_t *NGW, int32_t *chunks)
 {
     const int npan = (na_max + 31) / 32;
     const int per_wg = RM_WAVES * RM_MP;
-    const int NGW = (npan + per_wg - 1) / per_wg;
+    const int ngw = std::max(1, (npan + per_wg - 1) / per_wg);
     const int64_t NT = (n_max + 31) / 32 + 1;                      // + a partial settled tile
-    // about one workgroup per CU (256 CUs) unless BM_RANGE_WORKGROUPS says otherwise
-    static const int64_t env_wg = [] {
-        const char *e = getenv("BM_RANGE_WORKGROUPS");
-        return e ? atoll(e) : 0LL;
-    }();
-    const int64_t target_wg = env_wg > 0 ? env_wg : 256;
-    int64_t chunks = (target_wg + NGW - 1) / NGW;
-    if (chunks > NT) chunks = NT;
-    chunks = (chunks + 7) / 8 * 8;                                  // whole XCD rounds
-    const int64_t wgs = (int64_t)NGW * chunks;
+    int64_t ch = (target_wg + ngw - 1) / ngw;
+    if (ch > NT) ch = NT;
+    ch = std::max<int64_t>(8, (ch + 7) / 8 * 8);                  // whole XCD rounds
+    *NGW = ngw;
+    *chunks = (int32_t)ch;
+}
+
+template <int KS, bool F16, bool CONFLICT, bool CHUNKED>
+static hipError_t launch_ks(const RangeTask *tasks, const int32_t *task_of, int64_t wgs, int S, int nch,
+                            hipStream_t s, LaunchEvents ev)
+{
     constexpr int TPS = stage_tiles(CHUNKED, KS);
-    const size_t shmem = (size_t)2 * TPS * (a.S * 64 * 16 + 24 * 16) + 2 * RM_THREADS * sizeof(float);
-    hipExtLaunchKernelGGL(k_range_mfma<KS, F16, CONFLICT, CHUNKED>, dim3((unsigned)wgs), dim3(RM_THREADS),
-                          (uint32_t)shmem, s, ev.start, ev.stop, 0, a, P, n_dev, e2, A, blk, o, sd, C32, c32_stride,
-                          rowflag, NGW, (int)chunks, nch, ev.clock);
+    const size_t shmem = std::max(range_lds_bytes(S, TPS),
+                                  std::max(open_lds_bytes<RM_THREADS>(), accept_lds_bytes<RM_THREADS>()));
+    if (ev.start || ev.stop)          // events attached to the dispatch (not capturable in a graph)
+        hipExtLaunchKernelGGL(k_range_mfma<KS, F16, CONFLICT, CHUNKED>, dim3((unsigned)wgs), dim3(RM_THREADS),
+                              (uint32_t)shmem, s, ev.start, ev.stop, 0, tasks, task_of, nch, ev.clock);
+    else
+        k_range_mfma<KS, F16, CONFLICT, CHUNKED><<<dim3((unsigned)wgs), dim3(RM_THREADS), (uint32_t)shmem, s>>>(
+            tasks, task_of, nch, ev.clock);
     return hipGetLastError();
 }
 
 template <bool F16, bool CONFLICT>
-static hipError_t dispatch(const MfmaArgs &a, const PointsView &P, const int32_t *n_dev, double e2, const int32_t *A,
-                           const int64_t *blk, int na_max, int64_t n_max, const RangeOut &o, const SettledSet &sd,
-                           uint32_t *C32, int c32_stride, int *rowflag, hipStream_t s, LaunchEvents ev)
+static hipError_t dispatch(const RangeTask *tasks, const int32_t *task_of, int64_t wgs, int S, hipStream_t s,
+                           LaunchEvents ev)
 {
-#define BM_KS(k) \
-    launch_ks<k, F16, CONFLICT, false>(a, P, n_dev, e2, A, blk, na_max, n_max, o, sd, C32, c32_stride, rowflag, 1, s, ev)
-    switch (a.S) {
+#define BM_KS(k) launch_ks<k, F16, CONFLICT, false>(tasks, task_of, wgs, S, 1, s, ev)
+    switch (S) {
     case 1: return BM_KS(1);
     case 2: return BM_KS(2);
     case 3: return BM_KS(3);
@@ -652,84 +772,22 @@ static hipError_t dispatch(const MfmaArgs &a, const PointsView &P, const int32_t
     case 6: return BM_KS(6);
     case 7: return BM_KS(7);
     case 8: return BM_KS(8);
-    default: return launch_ks<8, F16, CONFLICT, true>(a, P, n_dev, e2, A, blk, na_max, n_max, o, sd, C32, c32_stride,
-                                                      rowflag, (a.S + 7) / 8, s, ev);
+    default: return launch_ks<8, F16, CONFLICT, true>(tasks, task_of, wgs, S, (S + 7) / 8, s, ev);
     }
 #undef BM_KS
 }
 
-hipError_t launch_range_mfma(const MfmaArgs &a, const PointsView &P, double e2, const int32_t *A,
-                             const int64_t *blk, int na_max, const RangeOut &o, const SettledSet &sd, hipStream_t s,
-                             LaunchEvents ev)
+hipError_t launch_range_tasks(const RangeTask *tasks, const int32_t *task_of, int64_t total_wgs, int kind, int S,
+                              bool conflict, hipStream_t s, LaunchEvents ev)
 {
-    if (a.S > kMaxMfmaSteps) return hipErrorInvalidValue;
-    if (P.n <= 0 || na_max <= 0) return hipSuccess;
-    if (a.kind == MFMA_F16)
-        return dispatch<true, false>(a, P, nullptr, e2, A, blk, na_max, P.n, o, sd, nullptr, 0, nullptr, s, ev);
-    return dispatch<false, false>(a, P, nullptr, e2, A, blk, na_max, P.n, o, sd, nullptr, 0, nullptr, s, ev);
-}
-
-hipError_t launch_resolve_mfma(const MfmaArgs &packed, const PointsView &Pc, const int32_t *nc_dev, double e2, int B,
-                               uint32_t *C32, int *rowflag, GreedyState *st, hipStream_t s)
-{
-    if (packed.S > kMaxMfmaSteps) return hipErrorInvalidValue;
-    RangeOut o{nullptr, nullptr, 0, st, 0};
-    const SettledSet none{};
-    const int stride = 2 * ((B + 63) / 64);
-    if (packed.kind == MFMA_F16)
-        return dispatch<true, true>(packed, Pc, nc_dev, e2, nullptr, nullptr, B, B, o, none, C32, stride, rowflag, s, {});
-    return dispatch<false, true>(packed, Pc, nc_dev, e2, nullptr, nullptr, B, B, o, none, C32, stride, rowflag, s, {});
-}
-
-// Copy the gathered candidates' operands and scalars into a packed set
-// (candidate j in place of rank j) for the resolve, and their original indices.
-__global__ void k_pack_candidates(MfmaArgs a, const int32_t *cand, const GreedyState *st, const int32_t *perm, int B,
-                                  MfmaArgs out, int32_t *cand_orig)
-{
-    const int nc = st->nc;
-    const int S = a.S;
-    const int64_t Bp = ((B + 31) / 32) * 32;
-    const int64_t nvec = Bp * S * 2;                 // (candidate, step, half) 16-byte vectors
-    const bool two = a.Qop != a.Pop;
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < nvec + Bp;
-         g += (int64_t)gridDim.x * blockDim.x) {
-        if (g < nvec) {
-            const int half = (int)(g & 1);
-            const int64_t js = g >> 1;
-            const int st_ = (int)(js % S);
-            const int64_t j = js / S;
-            const int64_t dst = ((((j >> 5) * S + st_) * 64) + (j & 31) + 32 * half) * 8;
-            u32x4 vp = {0u, 0u, 0u, 0u}, vq = {0u, 0u, 0u, 0u};
-            if (j < nc) {
-                const int64_t r = cand[j];
-                const int64_t src = ((((r >> 5) * S + st_) * 64) + (r & 31) + 32 * half) * 8;
-                vp = *(const u32x4 *)(a.Pop + src);
-                if (two) vq = *(const u32x4 *)(a.Qop + src);
-            }
-            *(u32x4 *)((uint16_t *)out.Pop + dst) = vp;
-            if (two) *(u32x4 *)((uint16_t *)out.Qop + dst) = vq;
-        } else {
-            const int64_t j = g - nvec;
-            const bool v = j < nc;
-            const int32_t r = v ? cand[j] : 0;
-            ((float *)out.cinit)[j] = v ? a.cinit[r] : 0.f;
-            ((float *)out.nuup)[j] = v ? a.nuup[r] : 0.f;
-#pragma unroll
-            for (int w = 0; w < 3; ++w) ((float *)out.T3)[t3_index(j, w)] = v ? a.T3[t3_index(r, w)] : INFINITY;
-            cand_orig[j] = v ? (perm ? perm[r] : r) : 0;
-        }
-    }
-}
-
-hipError_t launch_pack_candidates(const MfmaArgs &a, const int32_t *cand, const GreedyState *st, const int32_t *perm,
-                                  int B, const MfmaArgs &out, int32_t *cand_orig, hipStream_t s)
-{
-    const int64_t Bp = ((B + 31) / 32) * 32;
-    const int64_t total = Bp * a.S * 2 + Bp;
-    int64_t blocks = (total + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    k_pack_candidates<<<(int)blocks, 256, 0, s>>>(a, cand, st, perm, B, out, cand_orig);
-    return hipGetLastError();
+    if (S < 1 || S > kMaxMfmaSteps) return hipErrorInvalidValue;
+    if (total_wgs <= 0) return hipSuccess;
+    if (total_wgs > 0x7fffffffLL) return hipErrorInvalidValue;
+    const bool f16 = kind == MFMA_F16;
+    if (conflict) return f16 ? dispatch<true, true>(tasks, task_of, total_wgs, S, s, ev)
+                             : dispatch<false, true>(tasks, task_of, total_wgs, S, s, ev);
+    return f16 ? dispatch<true, false>(tasks, task_of, total_wgs, S, s, ev)
+               : dispatch<false, false>(tasks, task_of, total_wgs, S, s, ev);
 }
 
 } // namespace bm
