@@ -17,257 +17,15 @@
 #include "bm.h"
 #include "bm_internal.h"
 #include "bounds.h"
+#include "batch.h"
+#include "host_common.h"
 #include "kernels.h"
 
 using namespace bm;
 
 namespace {
 
-thread_local std::string g_last_error;
-
-struct BmError {
-    int code;
-    std::string msg;
-};
-
-[[noreturn]] void fail(int code, const std::string &msg) { throw BmError{code, msg}; }
-
-void hip_ok(hipError_t e, const char *what)
-{
-    if (e != hipSuccess) {
-        if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
-            fail(BM_ENOMEM, std::string(what) + ": " + hipGetErrorString(e));
-        fail(BM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
-    }
-}
-
-using clk = std::chrono::steady_clock;
-double ms_since(clk::time_point t0) { return std::chrono::duration<double, std::milli>(clk::now() - t0).count(); }
-
-size_t dtype_size(int32_t dtype) { return dtype == BM_F64 ? 8 : dtype == BM_F32 ? 4 : 2; }
-
-int bitlen(uint64_t v) { return v ? 64 - __builtin_clzll(v) : 0; }
-
-// ---- device context: selected device, stream, tracked allocations ------------------------
-constexpr size_t kPinnedBytes = 64 * 1024;
-constexpr size_t kUploadStage = kPinnedBytes - 4096;
-constexpr int kUploadBlocks = 64;                   // blocks per table of directly launched passes
-static_assert(kUploadBlocks * 32 <= 2048, "block table staging");
-static_assert(kUploadBlocks * sizeof(RangeTask) <= kUploadStage, "task staging");
-struct Device {
-    int dev = 0, prev_dev = -1;
-    hipStream_t s = nullptr;
-    bool own_stream = false;
-    int64_t budget = 0, used = 0;
-    std::vector<std::pair<void *, size_t>> bufs;
-    void *pinned = nullptr;
-
-    explicit Device(const bm_options &o)
-    {
-        int count = 0;
-        if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) fail(BM_ENODEVICE, "no HIP device is visible");
-        hip_ok(hipGetDevice(&prev_dev), "hipGetDevice");
-        dev = o.device < 0 ? prev_dev : o.device;
-        if (dev >= count) fail(BM_ENODEVICE, "options.device is out of range");
-        hip_ok(hipSetDevice(dev), "hipSetDevice");
-        budget = o.max_device_bytes;
-        if (o.stream) {
-            s = (hipStream_t)o.stream;
-        } else {
-            hip_ok(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
-            own_stream = true;
-        }
-        hip_ok(hipHostMalloc(&pinned, kPinnedBytes, hipHostMallocDefault), "hipHostMalloc");
-    }
-    ~Device()
-    {
-        if (s) (void)hipStreamSynchronize(s);
-        for (auto &b : bufs) (void)hipFree(b.first);
-        if (pinned) (void)hipHostFree(pinned);
-        if (own_stream && s) (void)hipStreamDestroy(s);
-        if (prev_dev >= 0) (void)hipSetDevice(prev_dev);
-    }
-    Device(const Device &) = delete;
-    Device &operator=(const Device &) = delete;
-
-    void *raw_alloc(size_t bytes, bool tracked)
-    {
-        if (bytes == 0) bytes = 16;
-        if (budget > 0 && used + (int64_t)bytes > budget)
-            fail(BM_ENOMEM, "device memory cap (options.max_device_bytes) exceeded");
-        void *p = nullptr;
-        hipError_t e = hipMalloc(&p, bytes);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            fail(BM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-        }
-        used += (int64_t)bytes;
-        if (tracked) bufs.emplace_back(p, bytes);
-        return p;
-    }
-    template <class T> T *alloc(size_t count) { return (T *)raw_alloc(count * sizeof(T), true); }
-    template <class T> T *zeros(size_t count)
-    {
-        T *p = alloc<T>(count);
-        hip_ok(hipMemsetAsync(p, 0, std::max<size_t>(count * sizeof(T), 1), s), "hipMemsetAsync");
-        return p;
-    }
-    void release(void *p)
-    {
-        for (size_t i = 0; i < bufs.size(); ++i)
-            if (bufs[i].first == p) {
-                (void)hipFree(p);
-                used -= (int64_t)bufs[i].second;
-                bufs.erase(bufs.begin() + (long)i);
-                return;
-            }
-    }
-    // stop tracking (ownership moves to a result)
-    void detach(void *p)
-    {
-        for (size_t i = 0; i < bufs.size(); ++i)
-            if (bufs[i].first == p) {
-                bufs.erase(bufs.begin() + (long)i);
-                return;
-            }
-    }
-    void sync() { hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"); }
-    // Pinned host memory: [0, 4 KB) staging of small reads and block tables,
-    // [4 KB, kPinnedBytes) staging of uploads.  Both wait for their copy.
-    template <class T> T fetch(const T *dptr)
-    {
-        static_assert(sizeof(T) <= 2048, "fetch staging");
-        hip_ok(hipMemcpyAsync((char *)pinned + 2048, dptr, sizeof(T), hipMemcpyDeviceToHost, s), "hipMemcpyAsync D2H");
-        sync();
-        T v;
-        std::memcpy(&v, (char *)pinned + 2048, sizeof(T));
-        return v;
-    }
-    void upload(void *dptr, const void *src, size_t bytes)
-    {
-        for (size_t off = 0; off < bytes; off += kUploadStage) {
-            const size_t m = std::min(kUploadStage, bytes - off);
-            sync();                                     // the staging area is free again
-            std::memcpy((char *)pinned + 4096, (const char *)src + off, m);
-            hip_ok(hipMemcpyAsync((char *)dptr + off, (char *)pinned + 4096, m, hipMemcpyHostToDevice, s),
-                   "hipMemcpyAsync H2D");
-        }
-        sync();
-    }
-};
-
-// ---- argument checks that need no device ----------------------------------------------
-void check_common(const void *points, int64_t n, int32_t d, int32_t dtype, double eps, const bm_options &o)
-{
-    if (n < 0) fail(BM_EINVAL, "n must be >= 0");
-    if (n > INT32_MAX) fail(BM_EINVAL, "n must be <= INT32_MAX");
-    if (d < 1) fail(BM_EINVAL, "d must be >= 1");
-    if (dtype != BM_F64 && dtype != BM_F32 && dtype != BM_F16) fail(BM_EINVAL, "unknown dtype");
-    if (!std::isfinite(eps) || !(eps > 0.0)) fail(BM_EINVAL, "eps must be finite and > 0");
-    if (!(eps * eps > 0.0)) fail(BM_EINVAL, "eps*eps underflows to 0 in FP64");
-    if (n > 0 && !points) fail(BM_EINVAL, "points is NULL");
-    if (o.path < BM_PATH_AUTO || o.path > BM_PATH_F16) fail(BM_EINVAL, "unknown path");
-    if (o.refine != 0 && o.refine != 1) fail(BM_EINVAL, "refine must be 0 or 1");
-    if (o.block < 0 || o.block > 4096) fail(BM_EINVAL, "block must be 0 (automatic) or 1..4096");
-    if (o.max_device_bytes < 0 || o.init_member_capacity < 0) fail(BM_EINVAL, "negative size option");
-    if ((o.profile != 0 && o.profile != 1) || (o.no_graph != 0 && o.no_graph != 1))
-        fail(BM_EINVAL, "profile and no_graph must be 0 or 1");
-}
-
-bool host_all_finite(const void *points, int64_t count, int32_t dtype)
-{
-    if (dtype == BM_F64) {
-        const double *p = (const double *)points;
-        for (int64_t i = 0; i < count; ++i)
-            if (!std::isfinite(p[i])) return false;
-    } else if (dtype == BM_F32) {
-        const float *p = (const float *)points;
-        for (int64_t i = 0; i < count; ++i)
-            if (!std::isfinite(p[i])) return false;
-    } else {
-        const uint16_t *p = (const uint16_t *)points;
-        for (int64_t i = 0; i < count; ++i)
-            if ((p[i] & 0x7c00u) == 0x7c00u) return false;
-    }
-    return true;
-}
-
-std::vector<int32_t> check_order(const int64_t *order, int64_t n)
-{
-    std::vector<int32_t> perm;
-    if (!order) return perm;
-    std::vector<uint8_t> seen((size_t)n, 0);
-    perm.resize((size_t)n);
-    for (int64_t r = 0; r < n; ++r) {
-        const int64_t p = order[r];
-        if (p < 0 || p >= n || seen[(size_t)p]) fail(BM_EINVAL, "order is not a permutation of 0..n-1");
-        seen[(size_t)p] = 1;
-        perm[(size_t)r] = (int32_t)p;
-    }
-    return perm;
-}
-
-struct Pair64 {
-    unsigned long long v[2];
-};
-
-int64_t range_target_wg()
-{
-    // about one workgroup per compute unit (256) unless BM_RANGE_WORKGROUPS says otherwise
-    static const int64_t env_wg = [] {
-        const char *e = getenv("BM_RANGE_WORKGROUPS");
-        return e ? atoll(e) : 0LL;
-    }();
-    return env_wg > 0 ? env_wg : 256;
-}
-
-// A captured sequence of kernels replayed as one HIP graph.  Captured on a
-// private stream (the caller's may be the legacy default stream, which cannot
-// be captured), launched on any stream.  No memset nodes are captured: the
-// block kernels clear what they need themselves.
-struct GraphRunner {
-    hipGraph_t g = nullptr;
-    hipGraphExec_t x = nullptr;
-    hipStream_t cs = nullptr;
-    bool ready() const { return x != nullptr; }
-    void reset()
-    {
-        if (x) (void)hipGraphExecDestroy(x);
-        if (g) (void)hipGraphDestroy(g);
-        x = nullptr;
-        g = nullptr;
-    }
-    template <class F> void capture(F &&enqueue)
-    {
-        reset();
-        if (!cs) hip_ok(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
-        hip_ok(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
-        try {
-            enqueue(cs);
-        } catch (...) {
-            hipGraph_t dead = nullptr;
-            (void)hipStreamEndCapture(cs, &dead);
-            if (dead) (void)hipGraphDestroy(dead);
-            throw;
-        }
-        hip_ok(hipStreamEndCapture(cs, &g), "end capture");
-        hip_ok(hipGraphInstantiate(&x, g, nullptr, nullptr, 0), "graph instantiate");
-    }
-    void launch(hipStream_t s) { hip_ok(hipGraphLaunch(x, s), "graph launch"); }
-    ~GraphRunner()
-    {
-        reset();
-        if (cs) (void)hipStreamDestroy(cs);
-    }
-};
-constexpr int kGraphBlocks = 8;                     // greedy blocks per captured graph
-
-bm_result *new_result()
-{
-    bm_result *r = (bm_result *)std::calloc(1, sizeof(bm_result));
-    if (!r) fail(BM_ENOMEM, "host allocation failed");
-    return r;
-}
+using namespace bm::host;
 
 // ---- one build ------------------------------------------------------------------------
 struct Job {
@@ -279,69 +37,6 @@ struct Job {
     const int32_t *fixed;          // fixed landmark list (original indices) or null
     int64_t n_fixed;
 };
-
-// gfx950 matrix cores take float16 (and bf16) subnormal operands exactly; the
-// device self-test (bm_device_selfcheck) verifies this before an MFMA path runs.
-constexpr bool kF16SubnormalsOk = true;
-
-std::mutex g_selfcheck_mu;
-std::map<int, int> g_selfcheck;     // device -> flags
-
-int device_flags(int dev, hipStream_t s)
-{
-    {
-        std::lock_guard<std::mutex> lk(g_selfcheck_mu);
-        auto it = g_selfcheck.find(dev);
-        if (it != g_selfcheck.end()) return it->second;
-    }
-    int *fd = nullptr;
-    hip_ok(hipMalloc(&fd, sizeof(int)), "hipMalloc");
-    int flags = 0;
-    hipError_t e = run_selfcheck(fd, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(&flags, fd, sizeof(int), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(fd);
-    hip_ok(e, "device self-check");
-    std::lock_guard<std::mutex> lk(g_selfcheck_mu);
-    g_selfcheck[dev] = flags;
-    return flags;
-}
-
-int auto_block(int64_t n, int path)
-{
-    if (path == BM_PATH_FP32) {
-        if (n >= (1 << 17)) return 1024;
-        if (n >= (1 << 13)) return 256;
-        return 64;
-    }
-    if (n >= (1 << 17)) return 4096;
-    if (n >= (1 << 13)) return 256;
-    return 64;
-}
-
-// Path choice from the band each path would have at the largest norm, relative
-// to eps^2: float16 storage -> F16 (exact operands); otherwise F16 on scaled
-// data when its band is under 2% of eps^2 (same matrix-core cost as BF16 with
-// an 8x narrower band), else the three-product BF16 split; FP32 when d is past
-// the matrix-core kernel's K.
-double band_fraction(int kind, int dtype, int d, double e2, double max_nu, double max_abs)
-{
-    const int K = ((kind == MFMA_BF16X3 ? 3 * d : d) + 15) / 16 * 16;
-    const double s = (kind == MFMA_F16) ? f16_scale(dtype, max_abs) : 1.0;
-    const MfmaBound b = mfma_bound(kind, d, K, e2 * s * s, std::sqrt(max_nu) * s, max_abs * s, true, dtype == BM_F16);
-    const double half_width = 2.0 * ((b.alpha + b.beta) * max_nu * s * s + b.abs_err);
-    return half_width / (e2 * s * s);
-}
-
-int auto_path(int dtype, int d, double e2, double max_nu, double max_abs)
-{
-    const int S1 = (d + 15) / 16, S3 = (3 * d + 15) / 16;
-    if (S1 > kMaxMfmaSteps) return BM_PATH_FP32;
-    if (dtype == BM_F16) return BM_PATH_F16;
-    if (band_fraction(MFMA_F16, dtype, d, e2, max_nu, max_abs) <= 0.02) return BM_PATH_F16;
-    if (S3 <= kMaxMfmaSteps) return BM_PATH_BF16X3;
-    return BM_PATH_F16;
-}
 
 bm_result *run_job(const Job &job, const bm_options &o)
 {
@@ -740,54 +435,21 @@ bm_result *run_job(const Job &job, const bm_options &o)
         // -- membership CSR
         const auto t_csr = clk::now();
         const int64_t M = (int64_t)hs.nkeys;
-        int64_t *row_ptr = dev.alloc<int64_t>((size_t)L + 1);
-        int32_t *midx = dev.alloc<int32_t>((size_t)std::max<int64_t>(M, 1));
-        uint64_t *skeys = dev.alloc<uint64_t>((size_t)std::max<int64_t>(M, 1));
         const int end_bit = bn + std::max(1, bitlen((uint64_t)L));
-        if (M > 0) {
-            size_t tb = 0;
-            hip_ok(sort_keys(nullptr, &tb, keys, skeys, (size_t)M, end_bit, dev.s), "sort size");
-            void *tmp = dev.raw_alloc(tb, true);
-            hip_ok(sort_keys(tmp, &tb, keys, skeys, (size_t)M, end_bit, dev.s), "sort");
-            dev.release(tmp);
-        }
-        hip_ok(launch_csr_from_sorted(skeys, M, L, bn, row_ptr, midx, dev.s), "csr");
+        uint64_t *skeys = sort_into(dev, keys, M, end_bit);
         dev.release(keys);
         keys = nullptr;
+        int64_t *row_ptr = nullptr;
+        int32_t *midx = nullptr;
+        csr_of(dev, skeys, M, L, bn, &row_ptr, &midx);
         dev.sync();
         res->stats.ms_csr = ms_since(t_csr);
 
         // -- edges
         const auto t_edges = clk::now();
-        int64_t E = 0;
         int32_t *edges = nullptr;
-        if (L > 1 && M > 0) {
-            int64_t *cnt = dev.zeros<int64_t>((size_t)n);
-            hip_ok(launch_point_degree(midx, M, cnt, dev.s), "point_degree");
-            int64_t *sptr = dev.alloc<int64_t>((size_t)n + 1);
-            size_t tb = 0;
-            hip_ok(scan_excl_i64(nullptr, &tb, cnt, sptr, (size_t)n, dev.s), "scan size");
-            void *tmp = dev.raw_alloc(std::max<size_t>(tb, (size_t)(L + 1) * 0 + 16), true);
-            hip_ok(scan_excl_i64(tmp, &tb, cnt, sptr, (size_t)n, dev.s), "scan");
-            dev.release(tmp);
-            int32_t *slist = dev.alloc<int32_t>((size_t)M);
-            hip_ok(hipMemsetAsync(cnt, 0, (size_t)n * 8, dev.s), "zero fill");
-            hip_ok(launch_fill_slists(skeys, M, bn, sptr, cnt, slist, dev.s), "fill_slists");
-            dev.release(cnt);
-            int64_t *deg = dev.alloc<int64_t>((size_t)L);
-            hip_ok(launch_edge_pass(0, L, row_ptr, midx, sptr, slist, deg, nullptr, nullptr, dev.s), "edge count");
-            int64_t *eptr = dev.alloc<int64_t>((size_t)L + 1);
-            tb = 0;
-            hip_ok(scan_excl_i64(nullptr, &tb, deg, eptr, (size_t)L, dev.s), "scan size");
-            tmp = dev.raw_alloc(tb, true);
-            hip_ok(scan_excl_i64(tmp, &tb, deg, eptr, (size_t)L, dev.s), "scan");
-            dev.release(tmp);
-            E = dev.fetch(eptr + L);
-            edges = dev.alloc<int32_t>((size_t)std::max<int64_t>(2 * E, 1));
-            if (E > 0)
-                hip_ok(launch_edge_pass(1, L, row_ptr, midx, sptr, slist, deg, eptr, edges, dev.s), "edge emit");
-            dev.sync();
-        }
+        const int64_t E = edges_of(dev, skeys, M, L, n, bn, row_ptr, midx, &edges, nullptr);
+        dev.sync();
         res->stats.ms_edges = ms_since(t_edges);
 
         // -- hand over
@@ -919,12 +581,33 @@ int bm_build_many(const bm_problem *probs, int32_t n_probs, const bm_options *op
             if (!o.points_on_device && pr.n > 0 && !host_all_finite(pr.points, pr.n * (int64_t)pr.d, pr.dtype))
                 fail(BM_ENONFINITE, "a coordinate is NaN or infinite");
         }
+        // chains of the problems that can share the device run as one batch;
+        // the rest (the plain FP32 path, d past the matrix-core K, n = 0) one by one
+        std::vector<const bm_problem *> bp;
+        std::vector<int64_t> slot0;
+        std::vector<char> in_batch((size_t)n_probs, 0);
         int64_t k = 0;
         for (int32_t p = 0; p < n_probs; ++p) {
+            if (batchable(probs[p], o)) {
+                bp.push_back(&probs[p]);
+                slot0.push_back(k);
+                in_batch[(size_t)p] = 1;
+            }
+            k += probs[p].n_eps;
+        }
+        if (!bp.empty() && !batch_fits(bp)) {
+            bp.clear();
+            slot0.clear();
+            std::fill(in_batch.begin(), in_batch.end(), 0);
+        }
+        if (!bp.empty()) run_batch(bp, slot0, o, outs);
+        k = 0;
+        for (int32_t p = 0; p < n_probs; ++p) {
             const bm_problem &pr = probs[p];
-            for (int32_t e = 0; e < pr.n_eps; ++e) {
+            for (int32_t e = 0; e < pr.n_eps; ++e, ++k) {
+                if (in_batch[(size_t)p]) continue;
                 Job job{pr.points, pr.n, pr.d, pr.dtype, pr.eps[e], pr.order, nullptr, 0};
-                outs[k++] = run_job(job, o);
+                outs[k] = run_job(job, o);
             }
         }
         return BM_OK;
@@ -940,6 +623,10 @@ int bm_build_many(const bm_problem *probs, int32_t n_probs, const bm_options *op
 void bm_result_free(bm_result *r)
 {
     if (!r) return;
+    if (r->on_device && unshare_result(r)) {       // a slice of a batch's arrays
+        std::free(r);
+        return;
+    }
     if (r->on_device) {
         int prev = -1;
         (void)hipGetDevice(&prev);

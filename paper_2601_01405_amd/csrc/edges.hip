@@ -4,7 +4,8 @@
 //
 // Built through the transpose of the membership CSR: S(x) lists the landmarks
 // whose ball holds x, and the neighbours j > i of landmark i are the union of
-// S(x) over x in its ball.  One workgroup per landmark deduplicates that union
+// S(x) over x in its ball.  Only rows with a member in some other ball are
+// visited (a work list built first); the others have no edge.  One workgroup per landmark deduplicates that union
 // either by sorting it in LDS (small unions) or with an LDS bitmap over the
 // range of j (large unions).  Rows come out in landmark order and each row in
 // increasing j, so the list is lexicographic without a global sort.
@@ -84,7 +85,45 @@ constexpr int EP_THREADS = 256;
 constexpr int EP_CAP = 2048;                    // union sizes sorted in LDS
 constexpr int EP_WORDS = 4096;                  // bitmap words per chunk (262144 landmarks, 32 KB)
 
-__global__ __launch_bounds__(EP_THREADS) void k_edge_pass(int mode, const int64_t *row_ptr,
+// Rows that can have an edge: some member x of row i lies in another ball
+// (|S(x)| > 1).  flag[] must start at zero.
+__global__ void k_flag_rows(const uint64_t *keys, int64_t M, int32_t bn, const int64_t *sptr, int *flag)
+{
+    const uint64_t mask = (1ull << bn) - 1;
+    for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < M; m += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = keys[m];
+        const int64_t x = (int64_t)(k & mask);
+        if (sptr[x + 1] - sptr[x] > 1) flag[k >> bn] = 1;
+    }
+}
+
+// The flagged rows, in no particular order: list[0 .. *count).
+__global__ void k_list_rows(const int *flag, int64_t L, int32_t *list, unsigned long long *count)
+{
+    for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x; i0 < L; i0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = i0 + threadIdx.x;
+        const bool want = i < L && flag[i] != 0;
+        const unsigned long long pos = wave_append(count, want);
+        if (want) list[pos] = (int32_t)i;
+    }
+}
+
+hipError_t launch_edge_rows(const uint64_t *keys, int64_t M, int32_t bn, const int64_t *sptr, int64_t L, int *flag,
+                            int32_t *list, unsigned long long *count, hipStream_t s)
+{
+    if (L <= 0) return hipSuccess;
+    int64_t blocks = (M + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    if (M > 0) k_flag_rows<<<(int)blocks, 256, 0, s>>>(keys, M, bn, sptr, flag);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    blocks = (L + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    k_list_rows<<<(int)blocks, 256, 0, s>>>(flag, L, list, count);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(EP_THREADS) void k_edge_pass(int mode, const int32_t *rows, const int64_t *row_ptr,
                                                           const int32_t *member_idx, const int64_t *sptr,
                                                           const int32_t *slist, int64_t *deg,
                                                           const int64_t *eptr, int32_t *edges)
@@ -93,7 +132,7 @@ __global__ __launch_bounds__(EP_THREADS) void k_edge_pass(int mode, const int64_
     __shared__ unsigned long long bits[EP_WORDS];
     __shared__ int sh_cnt, sh_min, sh_max;
     __shared__ int64_t sh_scan[EP_THREADS / 64];
-    const int32_t i = (int32_t)blockIdx.x;
+    const int32_t i = rows ? rows[blockIdx.x] : (int32_t)blockIdx.x;
     const int64_t m0 = row_ptr[i], m1 = row_ptr[i + 1];
     if (threadIdx.x == 0) {
         sh_cnt = 0;
@@ -220,12 +259,13 @@ __global__ __launch_bounds__(EP_THREADS) void k_edge_pass(int mode, const int64_
     if (mode == 0 && threadIdx.x == 0) deg[i] = written;
 }
 
-hipError_t launch_edge_pass(int mode, int64_t L, const int64_t *row_ptr, const int32_t *member_idx,
-                            const int64_t *sptr, const int32_t *slist, int64_t *deg, const int64_t *eptr,
-                            int32_t *edges, hipStream_t s)
+hipError_t launch_edge_pass(int mode, int64_t nrows, const int32_t *rows, const int64_t *row_ptr,
+                            const int32_t *member_idx, const int64_t *sptr, const int32_t *slist, int64_t *deg,
+                            const int64_t *eptr, int32_t *edges, hipStream_t s)
 {
-    if (L <= 0) return hipSuccess;
-    k_edge_pass<<<(unsigned)L, EP_THREADS, 0, s>>>(mode, row_ptr, member_idx, sptr, slist, deg, eptr, edges);
+    if (nrows <= 0) return hipSuccess;
+    k_edge_pass<<<(unsigned)nrows, EP_THREADS, 0, s>>>(mode, rows, row_ptr, member_idx, sptr, slist, deg, eptr,
+                                                       edges);
     return hipGetLastError();
 }
 

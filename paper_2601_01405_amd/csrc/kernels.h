@@ -81,9 +81,26 @@ hipError_t launch_point_degree(const int32_t *member_idx, int64_t M, int64_t *cn
 // S(x): the landmarks whose ball holds x, from the sorted membership keys.
 hipError_t launch_fill_slists(const uint64_t *keys, int64_t M, int32_t bn, const int64_t *sptr,
                               int64_t *sfill, int32_t *slist, hipStream_t s);
-// mode 0: deg[i] = number of neighbours j > i;  mode 1: write them at eptr[i].
-hipError_t launch_edge_pass(int mode, int64_t L, const int64_t *row_ptr, const int32_t *member_idx,
-                            const int64_t *sptr, const int32_t *slist, int64_t *deg,
+// Work list of the edge pass: rows i with a member x in some other ball
+// (|S(x)| > 1), from the sorted keys; flag[L] and *count must start at zero.
+hipError_t launch_edge_rows(const uint64_t *keys, int64_t M, int32_t bn, const int64_t *sptr, int64_t L, int *flag,
+                            int32_t *list, unsigned long long *count, hipStream_t s);
+// Over the rows rows[0..nrows) (null: 0..nrows-1).  mode 0: deg[i] = number of
+// neighbours j > i;  mode 1: write them at eptr[i].
+hipError_t launch_edge_pass(int mode, int64_t nrows, const int32_t *rows, const int64_t *row_ptr,
+                            const int32_t *member_idx, const int64_t *sptr, const int32_t *slist, int64_t *deg,
                             const int64_t *eptr, int32_t *edges, hipStream_t s);
+
+// ---- batches (batch.hip) ---------------------------------------------------------------------
+// Sorted chain-tagged keys (chain << (bl + bn) | ordinal << bn | index) into the
+// disjoint union: (lm_off[chain] + ordinal) << bnu | (pt_off[chain] + index).
+hipError_t launch_union_keys(uint64_t *keys, int64_t M, int32_t bn, int32_t bl, const int64_t *lm_off,
+                             const int64_t *pt_off, int32_t bnu, hipStream_t s);
+// Per chain: union landmarks, rebased row pointers (L_c + 1 at lm_off[c] + c),
+// columns and edges in the chain's own numbering, and ranges[4c..4c+3] = its
+// member range and edge range in the union arrays.
+hipError_t launch_rebase_chains(int nchains, const int32_t *const *lm, const int64_t *lm_off, const int64_t *pt_off,
+                                const int64_t *row_ptr, int32_t *midx, const int64_t *eptr, int32_t *edges,
+                                int32_t *lm_union, int64_t *mp_union, int64_t *ranges, hipStream_t s);
 
 } // namespace bm
