@@ -35,7 +35,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="clusters16d_n200k_f32")
+    ap.add_argument("--workload", default="clusters16d_n200k_f32",
+                    help="a named single-cloud workload, or 'batched' (256 clouds x 8 radii)")
     ap.add_argument("--path", default="auto", help="refined path (auto, bf16, bf16x3, f16)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
@@ -178,6 +179,97 @@ def summarize_trace(db, out, command):
     print("\n".join(lines))
 
 
+def range_roofline(runs, d, used_path, steps):
+    """Roofline entry of the range pass from profiled runs (device-clock windows)."""
+    range_ms = sum(s["ms_range_kernel"] for run in runs for s in run)
+    launches = sum(s["range_launches"] for run in runs for s in run)
+    range_pairs = sum(s["range_pairs"] for run in runs for s in run)
+    flops = 2.0 * d * range_pairs
+    achieved = flops / (range_ms * 1e-3) / 1e12 if range_ms > 0 else None
+    peak = PEAK_F16_TFLOPS if used_path == "f16" else PEAK_BF16_TFLOPS
+    return {"bound": "mfma", "kernel": "k_range_mfma", "achieved": achieved, "peak": peak,
+            "unit": "TFLOP/s", "frac": (achieved / peak) if achieved else None,
+            "traffic": read_traffic(range_pairs / max(launches, 1)),
+            "per_launch_ms": range_ms / max(launches, 1),
+            "launches_per_step": launches / steps,
+            "flops_per_pair": 2 * d, "pairs_per_launch": range_pairs / max(launches, 1),
+            "timing": "per_launch_ms: execution window of each range-pass launch on the device clock "
+                      "(first wave start to last wave end), summed over a profiled repeat of the timed "
+                      "steps; achieved = 2 d flops per landmark-point pair of those launches / that time"}
+
+
+def bench_batched(args):
+    """The batched workload: 256 seeded Gaussian mixtures (n log-uniform in
+    [1000, 200000], d in {8, 32, 96}) x 8 radii, one bm_build_many per step."""
+    import numpy as np
+    import torch
+
+    import paper_2601_01405_amd as bm
+    from paper_2601_01405_amd import workloads as W
+
+    probs = W.batched()
+    ntot = sum(p.points.shape[0] for p in probs)
+    log(f"workload batched: {len(probs)} clouds, sum n = {ntot}, 8 radii each")
+    dev = [(torch.from_numpy(p.points).cuda(), p.eps) for p in probs]
+    torch.cuda.synchronize()
+
+    def step(profile=False):
+        res = bm.build_many(dev, results_on_device=True, profile=profile)
+        st = [r.stats for row in res for r in row]
+        for row in res:
+            for r in row:
+                r.free()
+        return st
+
+    # parity of the same batch (host results), outside the timed region: the three
+    # smallest clouds in full against the oracle at three radii each, and sampled
+    # rows of the largest cloud at its smallest and largest radius
+    import oracle
+    exact = True
+    host = bm.build_many(dev)
+    order = np.argsort([p.points.shape[0] for p in probs])
+    for i in order[:3]:
+        p, row = probs[i], host[i]
+        for eps, got in zip(p.eps[::3], row[::3]):
+            ref = oracle.build(p.points, eps)
+            for name in ("landmarks", "member_ptr", "member_idx", "edges"):
+                exact &= bool(np.array_equal(getattr(got, name), getattr(ref, name)))
+    big = int(order[-1])
+    rng = np.random.default_rng(0)
+    for j in (0, len(probs[big].eps) - 1):
+        got = host[big][j]
+        pick = rng.choice(got.n_landmarks, min(8, got.n_landmarks), replace=False)
+        ref = oracle.range_sets(probs[big].points, got.landmarks[pick], probs[big].eps[j])
+        for k, i in enumerate(pick):
+            exact &= bool(np.array_equal(got.row(int(i)), ref.row(k)))
+    del host
+    log(f"bit-exact (3 smallest clouds in full, sampled rows of the largest): {exact}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    pairs = sum(s["pairs_useful"] for run in runs for s in run)
+    value = pairs / elapsed / 1e9
+    paths = {}
+    for p, s in zip([p for p in probs for _ in p.eps], runs[0]):
+        key = f"d={p.points.shape[1]}:{s['path']}"
+        paths[key] = paths.get(key, 0) + 1
+    log(f"batched: {value:.1f} G pair-dists/s, {elapsed / args.steps * 1e3:.1f} ms/step, paths {paths}")
+    line = {
+        "metric": METRIC + " (batched sweep)", "value": value, "unit": "G pair-dists/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16/f16",
+        "data": "synthetic",
+        "config": {"workload": "batched_256x8", "clouds": len(probs), "sum_n": ntot, "radii": 8,
+                   "chains": sum(len(p.eps) for p in probs), "paths": paths},
+        "graph_ms": runs[0][0]["ms_total"], "bit_exact": exact,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.summarize_traffic:
@@ -190,6 +282,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
+    if args.workload == "batched":
+        bench_batched(args)
+        return
     import numpy as np
     import torch
 
@@ -208,7 +303,7 @@ def main():
         out = []
         for eps in eps_list:
             r = bm.build(xd, eps, path=path, block=args.block, results_on_device=True, profile=profile)
-            out.append((r.stats, r.n_landmarks, r.n_edges))
+            out.append(dict(r.stats, n_landmarks=r.n_landmarks, n_edges=r.n_edges))
             r.free()
         return out
 
@@ -235,34 +330,30 @@ def main():
             exact &= bool(np.array_equal(a.row(int(i)), ref.row(j)))
     log(f"bit-exact (paths identical, sampled rows equal the oracle): {exact}")
 
-    # -- refined path, timed
+    # -- refined path, timed (the product path: no profiling)
     for _ in range(args.warmup):
         step(args.path)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    runs = [step(args.path, profile=True) for _ in range(args.steps)]
+    runs = [step(args.path) for _ in range(args.steps)]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    pairs = sum(s["pairs_useful"] for run in runs for s, _, _ in run)
+    pairs = sum(s["pairs_useful"] for run in runs for s in run)
     value = pairs / elapsed / 1e9
-    used_path = runs[0][0][0]["path"]
-    block = runs[0][0][0]["block"]
-    graph_ms = {f"eps={eps}": float(np.median([run[i][0]["ms_total"] for run in runs]))
+    used_path = runs[0][0]["path"]
+    block = runs[0][0]["block"]
+    graph_ms = {f"eps={eps}": float(np.median([run[i]["ms_total"] for run in runs]))
                 for i, eps in enumerate(eps_list)}
-    range_ms = sum(s["ms_range_kernel"] for run in runs for s, _, _ in run)
-    range_ev_ms = sum(s["ms_range_events"] for run in runs for s, _, _ in run)
-    launches = sum(s["range_launches"] for run in runs for s, _, _ in run)
-    range_pairs = sum(s["range_pairs"] for run in runs for s, _, _ in run)
-    log(f"refined {used_path}: {value:.1f} G pair-dists/s, {elapsed / args.steps * 1e3:.2f} ms/step, "
-        f"range kernels {range_ms / args.steps:.2f} ms/step over {launches // args.steps} launches")
-    # the same steps without the per-dispatch events, to show what timing them costs
+    log(f"refined {used_path}: {value:.1f} G pair-dists/s, {elapsed / args.steps * 1e3:.2f} ms/step")
+    # -- the same steps again with the range passes' device-clock windows recorded
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(args.path)
+    pruns = [step(args.path, profile=True) for _ in range(args.steps)]
     torch.cuda.synchronize()
-    plain_ms = (time.perf_counter() - t0) / args.steps * 1e3
-    log(f"same steps without kernel events: {plain_ms:.2f} ms/step")
+    prof_ms = (time.perf_counter() - t0) / args.steps * 1e3
+    roofline = range_roofline(pruns, d, used_path, args.steps)
+    log(f"profiled repeat: {prof_ms:.2f} ms/step, range passes {roofline['per_launch_ms'] * 1e3:.1f} us/launch, "
+        f"{roofline['achieved']:.1f} TFLOP/s algorithmic")
 
     # -- plain FP32 path on the same inputs
     fp32 = None
@@ -274,25 +365,9 @@ def main():
         fr = [step("fp32") for _ in range(fsteps)]
         torch.cuda.synchronize()
         fel = time.perf_counter() - t0
-        fpairs = sum(s["pairs_useful"] for run in fr for s, _, _ in run)
+        fpairs = sum(s["pairs_useful"] for run in fr for s in run)
         fp32 = {"value": fpairs / fel / 1e9, "ms_per_step": fel / fsteps * 1e3, "steps": fsteps}
         log(f"fp32: {fp32['value']:.1f} G pair-dists/s, {fp32['ms_per_step']:.2f} ms/step")
-
-    # -- roofline of the range pass (dominant kernel): algorithmic flops 2d per pair
-    flops = 2.0 * d * range_pairs
-    achieved = flops / (range_ms * 1e-3) / 1e12 if range_ms > 0 else None
-    peak = PEAK_F16_TFLOPS if used_path == "f16" else PEAK_BF16_TFLOPS
-    roofline = {"bound": "mfma", "kernel": "k_range_mfma", "achieved": achieved, "peak": peak,
-                "unit": "TFLOP/s", "frac": (achieved / peak) if achieved else None,
-                "traffic": read_traffic(range_pairs / max(launches, 1)),
-                "per_launch_ms": range_ms / max(launches, 1),
-                "per_launch_ms_events": range_ev_ms / max(launches, 1),
-                "launches_per_step": launches / args.steps,
-                "flops_per_pair": 2 * d, "pairs_per_launch": range_pairs / max(launches, 1),
-                "timing": "per_launch_ms: execution window of each range-pass launch on the device clock "
-                          "(first wave start to last wave end), summed over the timed steps; "
-                          "per_launch_ms_events: HIP events on the library stream around the same launches, "
-                          "which also hold each dispatch's wait behind the previous kernel"}
 
     # -- the FP64 oracle on the host, a bounded sample of the same workload
     cpu = None
@@ -319,8 +394,8 @@ def main():
         "config": {"workload": args.workload, "n": n, "d": d, "storage": str(x.dtype), "eps": eps_list,
                    "path": used_path, "block": block, "order": "index"},
         "graph_ms": graph_ms,
-        "ms_per_step_without_events": plain_ms,
-        "landmarks": [s[1] for s in runs[0]], "edges": [s[2] for s in runs[0]],
+        "ms_per_step_profiled": prof_ms,
+        "landmarks": [s["n_landmarks"] for s in runs[0]], "edges": [s["n_edges"] for s in runs[0]],
         "fp32_path": fp32,
         "speedup_vs_fp32": (value / fp32["value"]) if fp32 else None,
         "bit_exact": exact,

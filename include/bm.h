@@ -71,8 +71,11 @@ typedef enum {           /* stored dtype of the points (row-major n x d)        
 } bm_dtype;
 
 typedef enum {           /* arithmetic of the range pass filter                              */
-    BM_PATH_AUTO = 0,    /* F16 for float16 storage; else F16 (scaled) or BF16X3 from the band
-                            each would have at the data's largest norm; FP32 past d = 480     */
+    BM_PATH_AUTO = 0,    /* F16 for float16 storage; else F16 (scaled) when its band at the
+                            data's largest norm is under 2% of eps^2; else BF16X3, except that
+                            past K = 48 for the split one sampled F16 pass (512 landmarks)
+                            measures the pairs F16 would recheck and F16 is taken when they
+                            are few; FP32 past d = 480                                       */
     BM_PATH_FP32 = 1,    /* FP32 direct difference on the vector ALUs (the plain baseline)   */
     BM_PATH_BF16 = 2,    /* one BF16 product per coordinate on MFMA, FP32 accumulation       */
     BM_PATH_BF16X3 = 3,  /* hi/lo BF16 split, three products per coordinate on MFMA          */

@@ -87,14 +87,29 @@ bm_result *run_job(const Job &job, const bm_options &o)
             std::memcpy(&max_nu, &raw[0], 8);
             std::memcpy(&max_abs, &raw[1], 8);
         }
-        if (path == BM_PATH_AUTO) path = auto_path(job.dtype, d, e2, max_nu, max_abs);
+        MfmaArgs ma{};
+        bool ma_ready = false;
+        if (path == BM_PATH_AUTO) {
+            path = auto_path(job.dtype, d, e2, max_nu, max_abs);
+            // the split costs three products per coordinate: past K = 48, see
+            // whether one scaled-F16 product leaves few enough pairs to recheck
+            if (path == BM_PATH_BF16X3 && n > 0 && split_is_costly(d)) {
+                MfmaArgs f = prepare_mfma(dev, P, nu, MFMA_F16, e2, max_nu, max_abs, o.refine);
+                if (prefer_f16(d, sample_band_rate(dev, P, f, e2))) {
+                    path = BM_PATH_F16;
+                    ma = f;
+                    ma_ready = true;
+                } else {
+                    release_mfma(dev, f);
+                }
+            }
+        }
         res->stats.path = path;
         const int B = o.block ? o.block : auto_block(n, path);
 
         // -- path preparation
         Fp32Thresholds thr32{};
         float *xf = nullptr;
-        MfmaArgs ma{};
         if (path == BM_PATH_FP32) {
             thr32 = fp32_thresholds(e2, d, job.dtype, std::sqrt(max_nu), max_abs);
             if (job.dtype == BM_F32 && !perm_d) {
@@ -103,33 +118,8 @@ bm_result *run_job(const Job &job, const bm_options &o)
                 xf = dev.alloc<float>((size_t)n * d);
                 hip_ok(launch_to_f32(P, xf, dev.s), "to_f32");
             }
-        } else if (n > 0) {
-            const int kind = path;   // BM_PATH_BF16/BF16X3/F16 share the MfmaKind values
-            const int Kraw = (kind == MFMA_BF16X3) ? 3 * d : d;
-            const int S = (Kraw + 15) / 16;
-            if (S > kMaxMfmaSteps) fail(BM_EINVAL, "d too large for this MFMA path (use FP32, or BF16 for d <= 480)");
-            const size_t words = mfma_operand_words(n, S);
-            uint16_t *Pop = dev.alloc<uint16_t>(words);
-            uint16_t *Qop = (kind == MFMA_BF16X3) ? dev.alloc<uint16_t>(words) : Pop;
-            // F16 on float32/float64 storage works in units scaled by a power of two
-            const double scale = (kind == MFMA_F16) ? f16_scale(job.dtype, max_abs) : 1.0;
-            hip_ok(launch_mfma_operands(P, kind, S, scale, Pop, Qop, dev.s), "mfma_operands");
-            const int flags = device_flags(dev.dev, dev.s);
-            if ((flags & 3) != 3) fail(BM_EINTERNAL, "matrix-core layout self-check failed on this device");
-            const double sc2 = scale * scale;
-            const MfmaBound mb = mfma_bound(kind, d, 16 * S, e2 * sc2, std::sqrt(max_nu) * scale, max_abs * scale,
-                                            (flags & 4) != 0, job.dtype == BM_F16);
-            float *sc = dev.alloc<float>((size_t)n * 2 + t3_floats(n));
-            hip_ok(launch_mfma_scalars(n, nu, sc2, mb, e2 * sc2, d, sc, sc + n, sc + 2 * n, dev.s), "mfma_scalars");
-            ma.Pop = Pop;
-            ma.Qop = Qop;
-            ma.cinit = sc;
-            ma.nuup = sc + n;
-            ma.T3 = sc + 2 * n;
-            ma.alpha = f32_up(mb.alpha);
-            ma.S = S;
-            ma.kind = kind;
-            ma.refine = o.refine;
+        } else if (n > 0 && !ma_ready) {
+            ma = prepare_mfma(dev, P, nu, path, e2, max_nu, max_abs, o.refine);
         }
         res->stats.ms_prepare = ms_since(t_prep);
 

@@ -148,15 +148,33 @@ void run_batch(const std::vector<const bm_problem *> &probs, const std::vector<i
         for (int e = 0; e < pr.n_eps; ++e) e2min = std::min(e2min, pr.eps[e] * pr.eps[e]);
         q.path = o.path != BM_PATH_AUTO ? o.path : auto_path(q.dtype, q.d, e2min, q.max_nu, q.max_abs);
         if (q.path == BM_PATH_FP32) fail(BM_EINTERNAL, "batched problem on the FP32 path");
+        const PointsView PV{q.X, q.n, q.d, q.dtype, q.perm};
+        bool have = false;
+        if (o.path == BM_PATH_AUTO && q.path == BM_PATH_BF16X3 && split_is_costly(q.d)) {
+            // one scaled-F16 product instead of the split if its band is thin at
+            // the sweep's largest radius
+            double e2max = 0.0;
+            for (int e = 0; e < pr.n_eps; ++e) e2max = std::max(e2max, pr.eps[e] * pr.eps[e]);
+            MfmaArgs f = prepare_mfma(dev, PV, q.nu, MFMA_F16, e2max, q.max_nu, q.max_abs, o.refine);
+            if (prefer_f16(q.d, sample_band_rate(dev, PV, f, e2max))) {
+                q.path = BM_PATH_F16;
+                q.Pop = q.Qop = (uint16_t *)f.Pop;
+                dev.release((void *)f.cinit);
+                have = true;
+            } else {
+                release_mfma(dev, f);
+            }
+        }
         const int Kraw = (q.path == MFMA_BF16X3) ? 3 * q.d : q.d;
         q.S = (Kraw + 15) / 16;
         if (q.S > kMaxMfmaSteps) fail(BM_EINVAL, "d too large for this MFMA path");
         q.scale = (q.path == MFMA_F16) ? f16_scale(q.dtype, q.max_abs) : 1.0;
-        const size_t words = mfma_operand_words(q.n, q.S);
-        q.Pop = dev.alloc<uint16_t>(words);
-        q.Qop = (q.path == MFMA_BF16X3) ? dev.alloc<uint16_t>(words) : q.Pop;
-        const PointsView PV{q.X, q.n, q.d, q.dtype, q.perm};
-        hip_ok(launch_mfma_operands(PV, q.path, q.S, q.scale, q.Pop, q.Qop, dev.s), "mfma_operands");
+        if (!have) {
+            const size_t words = mfma_operand_words(q.n, q.S);
+            q.Pop = dev.alloc<uint16_t>(words);
+            q.Qop = (q.path == MFMA_BF16X3) ? dev.alloc<uint16_t>(words) : q.Pop;
+            hip_ok(launch_mfma_operands(PV, q.path, q.S, q.scale, q.Pop, q.Qop, dev.s), "mfma_operands");
+        }
     }
 
     // ---- chains and their memory (three arenas: zeroed, +inf, uninitialised)

@@ -338,6 +338,98 @@ inline int auto_path(int dtype, int d, double e2, double max_nu, double max_abs)
 }
 
 
+// ---- matrix-core operands and the automatic path ---------------------------------------------
+// Operands of a matrix-core path (kind = BM_PATH_BF16 / BF16X3 / F16) and the
+// per-point scalars of radius e2 (squared, data units).
+inline MfmaArgs prepare_mfma(Device &dev, const PointsView &P, const double *nu, int kind, double e2, double max_nu,
+                             double max_abs, int refine)
+{
+    const int64_t n = P.n;
+    const int d = P.d;
+    const int Kraw = (kind == MFMA_BF16X3) ? 3 * d : d;
+    const int S = (Kraw + 15) / 16;
+    if (S > kMaxMfmaSteps) fail(BM_EINVAL, "d too large for this MFMA path (use FP32, or BF16 for d <= 480)");
+    const int flags = device_flags(dev.dev, dev.s);
+    if ((flags & 3) != 3) fail(BM_EINTERNAL, "matrix-core layout self-check failed on this device");
+    const size_t words = mfma_operand_words(n, S);
+    uint16_t *Pop = dev.alloc<uint16_t>(words);
+    uint16_t *Qop = (kind == MFMA_BF16X3) ? dev.alloc<uint16_t>(words) : Pop;
+    // F16 on float32/float64 storage works in units scaled by a power of two
+    const double scale = (kind == MFMA_F16) ? f16_scale(P.dtype, max_abs) : 1.0;
+    hip_ok(launch_mfma_operands(P, kind, S, scale, Pop, Qop, dev.s), "mfma_operands");
+    const double sc2 = scale * scale;
+    const MfmaBound mb = mfma_bound(kind, d, 16 * S, e2 * sc2, std::sqrt(max_nu) * scale, max_abs * scale,
+                                    (flags & 4) != 0, P.dtype == BM_F16);
+    float *sc = dev.alloc<float>((size_t)n * 2 + t3_floats(n));
+    hip_ok(launch_mfma_scalars(n, nu, sc2, mb, e2 * sc2, d, sc, sc + n, sc + 2 * n, dev.s), "mfma_scalars");
+    MfmaArgs ma{};
+    ma.Pop = Pop;
+    ma.Qop = Qop;
+    ma.cinit = sc;
+    ma.nuup = sc + n;
+    ma.T3 = sc + 2 * n;
+    ma.alpha = f32_up(mb.alpha);
+    ma.S = S;
+    ma.kind = kind;
+    ma.refine = refine;
+    return ma;
+}
+
+inline void release_mfma(Device &dev, const MfmaArgs &ma)
+{
+    if (ma.Qop != ma.Pop) dev.release((void *)ma.Qop);
+    dev.release((void *)ma.Pop);
+    dev.release((void *)ma.cinit);
+}
+
+// Fraction of landmark-point pairs a filter leaves to the FP64 recheck at
+// radius e2: one range pass of up to 512 landmarks at evenly spaced ranks
+// against every point, keeping no membership.
+inline double sample_band_rate(Device &dev, const PointsView &P, const MfmaArgs &ma, double e2)
+{
+    const int64_t n = P.n;
+    const int m = (int)std::min<int64_t>(n, 512);
+    if (m <= 0) return 0.0;
+    std::vector<int32_t> ranks((size_t)m);
+    for (int j = 0; j < m; ++j) ranks[(size_t)j] = (int32_t)(((int64_t)j * n) / m);
+    int32_t *A = dev.alloc<int32_t>((size_t)m);
+    int64_t *blk = dev.alloc<int64_t>(4);
+    GreedyState *st = dev.zeros<GreedyState>(1);
+    uint64_t *none = dev.alloc<uint64_t>(1);
+    const int64_t blk_h[4] = {0, m, 0, 0};
+    dev.upload(A, ranks.data(), (size_t)m * 4);
+    dev.upload(blk, blk_h, sizeof blk_h);
+    RangeTask t{};
+    t.a = ma;
+    t.P = P;
+    t.e2 = e2;
+    t.A = A;
+    t.blk = blk;
+    t.o = RangeOut{nullptr, none, 0, &st->nkeys, st, 0, 1};      // capacity 0: no key is kept
+    range_grid(m, n, range_target_wg(), &t.NGW, &t.chunks);
+    RangeTask *td = dev.alloc<RangeTask>(1);
+    dev.upload(td, &t, sizeof t);
+    hip_ok(launch_range_tasks(td, nullptr, (int64_t)t.NGW * t.chunks, ma.kind, ma.S, false, dev.s), "band probe");
+    const GreedyState h = dev.fetch(st);
+    for (void *ptr : {(void *)A, (void *)blk, (void *)st, (void *)none, (void *)td}) dev.release(ptr);
+    return (double)h.band / ((double)m * (double)n);
+}
+
+// The three-product split stops being almost free once its K passes 48 (below
+// that the pass is bound by its epilogue, not by the matrix cores).
+inline bool split_is_costly(int d) { return (3 * d + 15) / 16 > 3; }
+// Scaled F16 (one product) instead of the split when its sampled band rate is
+// below 5e-5 per matrix-core step saved: one FP64 recheck costs about as much
+// as the products of tens of thousands of pairs.  A split past K = 128 does not
+// fit the registers and reloads its landmark operands per point tile, which
+// makes each of its steps about three times as costly.
+inline bool prefer_f16(int d, double band_rate)
+{
+    const int S1 = (d + 15) / 16, S3 = (3 * d + 15) / 16;
+    const double split_steps = (S3 > 8) ? 3.0 * S3 : (double)S3;
+    return band_rate <= 5e-5 * (split_steps - S1);
+}
+
 // ---- results that share device arrays (a batch) ------------------------------------------
 // Device arrays holding the results of one batch; freed with the last of them.
 struct SharedResults {

@@ -480,7 +480,8 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
             if (have) {
                 xo = stl ? (int64_t)sd.idx[p] : orig_index(P, p);
                 const int32_t lr = A ? A[ai] : ai;
-                memb = exact_member(P, orig_index(P, lr), xo, e2);
+                // a landmark against its own point: s = 0 < e2
+                memb = (!stl && lr == p) || exact_member(P, orig_index(P, lr), xo, e2);
             }
             const uint64_t bal = __ballot(memb);
             if (!bal) continue;
