@@ -112,16 +112,40 @@ def is_range_pass(name):
     return len(ta) >= 3 and ta[2] == "false"
 
 
-def _dispatch_values(db, counter):
-    import sqlite3
-    con = sqlite3.connect(db)
+def _dispatch_values(path, counter):
+    """Per-dispatch values of one counter from a rocprofv3 --pmc output: the
+    counter_collection CSV (--output-format csv) or the SQLite database."""
     per = {}
+    if path.endswith(".csv"):
+        import csv
+        for row in csv.DictReader(open(path)):
+            if row.get("Counter_Name") != counter:
+                continue
+            key = (row["Kernel_Name"], row["Dispatch_Id"])
+            per[key] = per.get(key, 0.0) + float(row["Counter_Value"])
+        return per
+    import sqlite3
+    con = sqlite3.connect(path)
     for name, disp, value in con.execute(
             "select kernel_name, dispatch_id, value from counters_collection where counter_name = ?", (counter,)):
         key = (name, disp)
         per[key] = per.get(key, 0.0) + float(value)
     con.close()
     return per
+
+
+def _kernel_spans(path):
+    """(name, start_ns, end_ns) of every dispatch in a rocprofv3 kernel trace
+    (kernel_trace CSV or SQLite database)."""
+    if path.endswith(".csv"):
+        import csv
+        return [(r["Kernel_Name"], int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
+                for r in csv.DictReader(open(path))]
+    import sqlite3
+    con = sqlite3.connect(path)
+    rows = list(con.execute("select name, start, \"end\" from kernels"))
+    con.close()
+    return rows
 
 
 def summarize_traffic(fetch_db, write_db, out, command):
@@ -152,16 +176,13 @@ def summarize_traffic(fetch_db, write_db, out, command):
 
 
 def summarize_trace(db, out, command):
-    import sqlite3
-    con = sqlite3.connect(db)
     rows = {}
-    for name, start, end in con.execute("select name, start, \"end\" from kernels"):
+    for name, start, end in _kernel_spans(db):
         key = name.split("(")[0].replace("void ", "")
         if is_range_pass(name):
             key += "  [range pass]"
         c, t = rows.get(key, (0, 0.0))
         rows[key] = (c + 1, t + (end - start) / 1e3)
-    con.close()
     total = sum(t for _, t in rows.values()) or 1.0
     lines = [f"# Kernel trace summary (rocprofv3 --kernel-trace --stats), durations in microseconds",
              f"# command: {command}", "",

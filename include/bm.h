@@ -87,7 +87,7 @@ typedef enum {           /* arithmetic of the range pass filter                 
 typedef struct {
     int32_t path;                 /* bm_path                                                   */
     int32_t refine;               /* 1 = exact (FP64 recheck of the band), 0 = unrefined       */
-    int32_t block;                /* candidate block size B: 0 = automatic, else 1..4096        */
+    int32_t block;                /* candidate block size B: 0 = automatic, else 1..8192        */
     int32_t device;               /* HIP device ordinal; -1 = the calling thread's current one */
     int32_t points_on_device;     /* 1: `points` is a device pointer on options.device          */
     int32_t results_on_device;    /* 1: result arrays stay in device memory                    */
@@ -97,9 +97,10 @@ typedef struct {
     int32_t profile;              /* 1: time the range passes: device-clock execution windows,
                                      plus HIP events on `stream` around each directly launched
                                      pass (not around passes replayed from a graph)           */
-    int32_t no_graph;             /* 0: past its first few blocks the greedy replays a captured
-                                     HIP graph of the per-block kernels; 1: every kernel is
-                                     launched directly                                        */
+    int32_t no_graph;             /* 0: past its first few blocks the greedy of a cloud under
+                                     2^17 points, and every batch, replays a captured HIP graph
+                                     of the per-block kernels; 1: every kernel is launched
+                                     directly                                                 */
 } bm_options;
 
 typedef struct {

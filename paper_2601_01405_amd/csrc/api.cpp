@@ -355,7 +355,10 @@ bm_result *run_job(const Job &job, const bm_options &o)
             // no candidate and do nothing).  The FP32 pass takes its key buffer by
             // value, so a graph of that path is captured again when the buffer moves.
             GraphRunner gr;
-            const bool use_graph = !o.no_graph;
+            // Capturing and instantiating costs about as much as a few hundred
+            // microseconds of launches; it pays off where blocks are short (small
+            // clouds), not where every block runs for a hundred microseconds.
+            const bool use_graph = !o.no_graph && n < kGraphMaxPoints;
             // Blocks are queued back to back; the host looks at the state once per batch.
             int batch = 4;
             bool direct_batch = true;

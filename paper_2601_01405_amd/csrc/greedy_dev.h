@@ -16,10 +16,10 @@
 
 namespace bm {
 
-constexpr int MAX_B = 4096;
+constexpr int MAX_B = 8192;
 
 // LDS bytes the steps use (from a caller-provided, 16-byte aligned buffer).
-template <int NT> constexpr size_t open_lds_bytes() { return 16 + (size_t)NT / 64 * 4 + (size_t)NT * 4; }
+template <int NT> constexpr size_t open_lds_bytes() { return 16 + (size_t)NT / 64 * 4 + (size_t)NT * 16; }
 template <int NT> constexpr size_t accept_lds_bytes()
 {
     return (size_t)MAX_B / 64 * 16 + 16 + (size_t)NT / 64 * 4 + (size_t)MAX_B * 2;
@@ -98,29 +98,63 @@ __device__ void block_open(const ChainTask &T, unsigned char *lds)
 
     int64_t R1 = R0;
     if (T.settle && count > 0) {
+        // one bitmap word (64 ranks) per thread per round; the round's
+        // non-landmarks are listed in rank order, then their thresholds,
+        // indices and operands copied
         const MfmaArgs &a = T.a;
         const SettledSet &sd = T.sd;
         R1 = ((int64_t)*sh_first >> 5) << 5;
         const int S = a.S, nvec = 2 * S;
-        for (int64_t r0 = R0; r0 < R1; r0 += NT) {
-            const int64_t r = r0 + tid;
-            const bool take = r < R1 && !((T.islm[r >> 6] >> (r & 63)) & 1ull);
+        constexpr int kSel = NT * 4;                             // listed per pass of the copy
+        for (int64_t w0 = R0 >> 6; (w0 << 6) < R1; w0 += NT) {  // R0 is a multiple of 32
+            const int64_t w = w0 + tid;
+            uint64_t msk = 0;
+            if ((w << 6) < R1) {
+                msk = ~T.islm[w];
+                const int64_t lo = w << 6;
+                if (lo < R0) msk &= (~0ull) << (R0 - lo);        // R0 - lo is 0 or 32
+                if (R1 - lo < 64) msk &= (1ull << (R1 - lo)) - 1;
+            }
             int total;
-            const int pre = block_excl_scan<NT>((int)take, &total, sh_scan);
-            if (take) {
-                const int64_t j = m + pre;
-                sel[pre] = (int32_t)r;
+            const int pre = block_excl_scan<NT>((int)__popcll(msk), &total, sh_scan);
+            // thresholds and indices straight away; operands through the LDS list
+            for (int k = pre; msk; ++k) {
+                const int b = __ffsll((unsigned long long)msk) - 1;
+                msk &= msk - 1;
+                const int64_t r = (w << 6) + b;
+                const int64_t j = m + k;
 #pragma unroll
                 for (int q = 0; q < 3; ++q) sd.T3[t3_index(j, q)] = a.T3[t3_index(r, q)];
                 sd.idx[j] = T.perm ? T.perm[r] : (int32_t)r;
+                if (k < kSel) sel[k] = (int32_t)r;
             }
             __syncthreads();
-            for (int v = tid; v < total * nvec; v += NT) {
-                const int q = v / nvec, rem = v - q * nvec, ss = rem >> 1, half = rem & 1;
-                const int64_t src = sel[q], dst = m + q;
-                const int64_t so = ((((src >> 5) * S + ss) * 64) + (src & 31) + 32 * half) * 8;
-                const int64_t dof = ((((dst >> 5) * S + ss) * 64) + (dst & 31) + 32 * half) * 8;
-                *(u32x4 *)(sd.Pop + dof) = *(const u32x4 *)(a.Pop + so);
+            for (int q0 = 0; q0 < total; q0 += kSel) {
+                if (q0 > 0) {                                    // a long round: list the next part again
+                    __syncthreads();
+                    int k = pre;
+                    uint64_t mm = 0;
+                    if ((w << 6) < R1) {
+                        mm = ~T.islm[w];
+                        const int64_t lo = w << 6;
+                        if (lo < R0) mm &= (~0ull) << (R0 - lo);
+                        if (R1 - lo < 64) mm &= (1ull << (R1 - lo)) - 1;
+                    }
+                    for (; mm; ++k) {
+                        const int b = __ffsll((unsigned long long)mm) - 1;
+                        mm &= mm - 1;
+                        if (k >= q0 && k < q0 + kSel) sel[k - q0] = (int32_t)((w << 6) + b);
+                    }
+                    __syncthreads();
+                }
+                const int cnt = min(kSel, total - q0);
+                for (int v = tid; v < cnt * nvec; v += NT) {
+                    const int q = v / nvec, rem = v - q * nvec, ss = rem >> 1, half = rem & 1;
+                    const int64_t src = sel[q], dst = m + q0 + q;
+                    const int64_t so = ((((src >> 5) * S + ss) * 64) + (src & 31) + 32 * half) * 8;
+                    const int64_t dof = ((((dst >> 5) * S + ss) * 64) + (dst & 31) + 32 * half) * 8;
+                    *(u32x4 *)(sd.Pop + dof) = *(const u32x4 *)(a.Pop + so);
+                }
             }
             m += total;
             __syncthreads();
@@ -160,8 +194,8 @@ __device__ __forceinline__ uint64_t wave_or64(uint64_t x)
 // view only delays one; the earliest undecided candidate always has all its
 // conflicts decided, so every round decides at least one.  The result equals
 // the sequential scan.  Flagged candidates are listed first; in a round one
-// wave takes one flagged row, lane w reading conflict word w (one coalesced
-// load per row).  The accepted ranks go to A (the range pass's list), the
+// wave takes one flagged row, lane w reading conflict words w, w + 64
+// (coalesced loads).  The accepted ranks go to A (the range pass's list), the
 // landmark list (original indices) and lm_rank at ordinal st->L, and the
 // block is recorded in blog[(st->blocks - 1) % kBlockLogSize].
 template <int NT>
@@ -212,15 +246,19 @@ __device__ void block_accept(const ChainTask &T, unsigned char *lds)
                 __atomic_load_n(&acc[wj], __ATOMIC_RELAXED) | __atomic_load_n(&rej[wj], __ATOMIC_RELAXED);
             if (__ballot((dj & bit) != 0)) continue;             // decided (decisions are final)
             const int nwj = (j + 63) >> 6;                       // words holding candidates < j
-            unsigned long long c = 0, av = 0, rv = 0;
-            if (lane < nwj) {
-                c = C[(int64_t)j * nw + lane];
-                if (lane == wj) c &= bit - 1ull;                 // only i < j (the rest is not written)
-                av = __atomic_load_n(&acc[lane], __ATOMIC_RELAXED);
-                rv = __atomic_load_n(&rej[lane], __ATOMIC_RELAXED);
+            bool any_acc = false, any_open = false;
+            for (int w0 = 0; w0 < nwj; w0 += 64) {               // lane w reads word w0 + w
+                const int w = w0 + lane;
+                unsigned long long c = 0, av = 0, rv = 0;
+                if (w < nwj) {
+                    c = C[(int64_t)j * nw + w];
+                    if (w == wj) c &= bit - 1ull;                // only i < j (the rest is not written)
+                    av = __atomic_load_n(&acc[w], __ATOMIC_RELAXED);
+                    rv = __atomic_load_n(&rej[w], __ATOMIC_RELAXED);
+                }
+                any_acc = any_acc || __ballot((c & av) != 0ull) != 0;
+                any_open = any_open || __ballot((c & ~(av | rv)) != 0ull) != 0;
             }
-            const bool any_acc = __ballot((c & av) != 0ull) != 0;
-            const bool any_open = __ballot((c & ~(av | rv)) != 0ull) != 0;
             if (lane == 0) {
                 if (any_acc) atomicOr(&rej[wj], bit);
                 else if (!any_open) atomicOr(&acc[wj], bit);

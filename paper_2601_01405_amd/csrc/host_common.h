@@ -172,7 +172,7 @@ inline void check_common(const void *points, int64_t n, int32_t d, int32_t dtype
     if (n > 0 && !points) fail(BM_EINVAL, "points is NULL");
     if (o.path < BM_PATH_AUTO || o.path > BM_PATH_F16) fail(BM_EINVAL, "unknown path");
     if (o.refine != 0 && o.refine != 1) fail(BM_EINVAL, "refine must be 0 or 1");
-    if (o.block < 0 || o.block > 4096) fail(BM_EINVAL, "block must be 0 (automatic) or 1..4096");
+    if (o.block < 0 || o.block > 8192) fail(BM_EINVAL, "block must be 0 (automatic) or 1..8192");
     if (o.max_device_bytes < 0 || o.init_member_capacity < 0) fail(BM_EINVAL, "negative size option");
     if ((o.profile != 0 && o.profile != 1) || (o.no_graph != 0 && o.no_graph != 1))
         fail(BM_EINVAL, "profile and no_graph must be 0 or 1");
@@ -265,6 +265,7 @@ struct GraphRunner {
     }
 };
 constexpr int kGraphBlocks = 8;                     // greedy blocks per captured graph
+constexpr int64_t kGraphMaxPoints = 1 << 17;        // single builds replay graphs below this size
 
 inline bm_result *new_result()
 {
@@ -308,7 +309,7 @@ inline int auto_block(int64_t n, int path)
         if (n >= (1 << 13)) return 256;
         return 64;
     }
-    if (n >= (1 << 17)) return 4096;
+    if (n >= (1 << 17)) return 8192;
     if (n >= (1 << 13)) return 256;
     return 64;
 }
