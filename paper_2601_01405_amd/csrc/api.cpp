@@ -105,7 +105,7 @@ bm_result *run_job(const Job &job, const bm_options &o)
             }
         }
         res->stats.path = path;
-        const int B = o.block ? o.block : auto_block(n, path);
+        const int B = o.block ? o.block : auto_block(n, d, path);
 
         // -- path preparation
         Fp32Thresholds thr32{};
@@ -130,6 +130,12 @@ bm_result *run_job(const Job &job, const bm_options &o)
         unsigned long long cap = o.init_member_capacity
                                      ? (unsigned long long)o.init_member_capacity
                                      : (unsigned long long)std::max<int64_t>(2 * n, 1 << 16);
+        if (!o.init_member_capacity && ma.Pop && !job.fixed && n >= kProbePoints) {
+            // big clouds: the mean ball of 64 sampled landmarks sizes the buffer for
+            // the first blocks, so that they need no recompute after an overflow
+            const double ball = sample_pass(dev, P, ma, e2, 64).ball_mean;
+            cap = std::max<unsigned long long>(cap, (unsigned long long)(1.5 * ball * 4.0 * B) + 65536ull);
+        }
         uint64_t *keys = dev.alloc<uint64_t>(cap);
         GreedyState *st = dev.zeros<GreedyState>(1);
         const int64_t lm_cap = std::max<int64_t>(job.fixed ? job.n_fixed : n, 1);
@@ -237,16 +243,19 @@ bm_result *run_job(const Job &job, const bm_options &o)
         // the landmark ranges [L0_j, L0_j + na_j) from the first incomplete one on,
         // restarting the key counter where that block began.  The landmark set is
         // unaffected (covered bits do not depend on the key buffer).
-        auto refill = [&](const std::vector<BlockLog> &logs) {
-            const unsigned long long need = hs.nkeys;
-            const unsigned long long start = logs.front().nkeys_before;
-            const unsigned long long ncap = std::max<unsigned long long>(2 * cap, need + need / 2);
+        // A bigger key buffer holding the first `keep` keys of the old one.
+        auto grow_keys = [&](unsigned long long ncap, unsigned long long keep) {
             uint64_t *nk = dev.alloc<uint64_t>(ncap);
-            if (start) hip_ok(hipMemcpyAsync(nk, keys, start * 8, hipMemcpyDeviceToDevice, dev.s), "regrow copy");
+            if (keep) hip_ok(hipMemcpyAsync(nk, keys, keep * 8, hipMemcpyDeviceToDevice, dev.s), "regrow copy");
             dev.sync();
             dev.release(keys);
             keys = nk;
             cap = ncap;
+        };
+        auto refill = [&](const std::vector<BlockLog> &logs) {
+            const unsigned long long need = hs.nkeys;
+            const unsigned long long start = logs.front().nkeys_before;
+            grow_keys(std::max<unsigned long long>(2 * cap, need + need / 2), start);
             dev.upload(&st->nkeys, &start, 8);
             run_rows(logs, lm_rank);
             const GreedyState chk = dev.fetch(st);
@@ -360,11 +369,23 @@ bm_result *run_job(const Job &job, const bm_options &o)
             // clouds), not where every block runs for a hundred microseconds.
             const bool use_graph = !o.no_graph && n < kGraphMaxPoints;
             // Blocks are queued back to back; the host looks at the state once per batch.
-            int batch = 4;
+            // Batches of 1 and 3 blocks launched directly, then 8, 16, 32, 64.  Before
+            // each batch the key buffer grows to what the keys per landmark so far
+            // predict, so that an overflow (and its recompute) stays rare.
+            int batch = 1;
+            int nbatch = 0;
             bool direct_batch = true;
             void *graph_keys = nullptr;
             for (;;) {
                 const unsigned long long blocks_before = hs.accepted;
+                if (hs.L > 0) {
+                    const double per_lm = (double)hs.nkeys / (double)hs.L;
+                    const double want = (double)hs.nkeys + 1.25 * per_lm * (double)batch * (double)B + 65536.0;
+                    if (want > (double)cap) {
+                        grow_keys((unsigned long long)(want * 1.25), hs.nkeys);
+                        if (mfma) upload_tasks();       // the range task writes to the new buffer
+                    }
+                }
                 if (use_graph && !direct_batch) {
                     if (!gr.ready() || (!mfma && graph_keys != (void *)keys)) {
                         gr.capture([&](hipStream_t cs) {
@@ -377,7 +398,7 @@ bm_result *run_job(const Job &job, const bm_options &o)
                     for (int k = 0; k < batch; ++k) enqueue_block(dev.s, true);
                 }
                 res->stats.range_launches += batch;
-                direct_batch = false;
+                direct_batch = ++nbatch < 2;
                 hs = dev.fetch(st);
                 if (hs.error) fail(BM_EINTERNAL, "candidate acceptance did not converge");
                 if (hs.nkeys > cap) {
@@ -401,7 +422,7 @@ bm_result *run_job(const Job &job, const bm_options &o)
                     upload_tasks();                 // the greedy's pass writes to the new buffer
                 }
                 if (hs.done) break;
-                batch = std::min(batch * 2, 64);     // 8, 16, 32, 64: whole graphs
+                batch = nbatch == 1 ? 3 : nbatch == 2 ? 8 : std::min(batch * 2, 64);   // graphs: multiples of 8
             }
             L = hs.L;
             res->stats.blocks = (int64_t)hs.blocks;

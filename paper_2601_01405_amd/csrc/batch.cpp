@@ -59,8 +59,8 @@ int64_t chain_target_wg(int64_t n) { return std::max<int64_t>(8, std::min<int64_
 
 int32_t batch_block(int64_t n, int32_t d, int32_t path)
 {
-    (void)d;
     (void)path;
+    if (const int32_t B = tuned_block(n, d, true)) return B;
     if (n >= (1 << 17)) return 4096;
     if (n >= (1 << 15)) return 2048;
     if (n >= (1 << 13)) return 1024;
@@ -443,7 +443,7 @@ void run_batch(const std::vector<const bm_problem *> &probs, const std::vector<i
     const auto t_edges = clk::now();
     int32_t *edges = nullptr;
     int64_t *eptr = nullptr;
-    const int64_t Etot = edges_of(dev, skeys, (int64_t)M, Ltot, Ntot, bnu, row_ptr, midx, &edges, &eptr);
+    const int64_t Etot = edges_of(dev, skeys, (int64_t)M, Ltot, Ntot, bnu, row_ptr, midx, &edges, &eptr, lm_off_d, nch);
     dev.release(skeys);
     std::vector<const int32_t *> lm_ptrs((size_t)nch);
     for (int c = 0; c < nch; ++c) lm_ptrs[(size_t)c] = ch[(size_t)c].lm;

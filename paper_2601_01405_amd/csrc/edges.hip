@@ -123,68 +123,99 @@ hipError_t launch_edge_rows(const uint64_t *keys, int64_t M, int32_t bn, const i
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(EP_THREADS) void k_edge_pass(int mode, const int32_t *rows, const int64_t *row_ptr,
+// The union of S(x) over the members x of row i is walked as one flattened
+// sequence: members are taken EP_THREADS at a time, their list lengths scanned
+// into LDS offsets, and thread e of the workgroup reads entry e, e + EP_THREADS,
+// ... of the concatenated lists (a binary search in the offsets finds its
+// member), so the loads of consecutive threads are consecutive in slist and
+// many are in flight.  visit(j) is called for every entry j > i.
+template <class F>
+__device__ __forceinline__ void walk_union(int32_t i, int64_t m0, int64_t m1, const int32_t *member_idx,
+                                           const int64_t *sptr, const int32_t *slist, int64_t *sh_off,
+                                           int64_t *sh_s0, int64_t *sh_scan, F &&visit)
+{
+    const int tid = (int)threadIdx.x;
+    for (int64_t mc = m0; mc < m1; mc += EP_THREADS) {
+        const int64_t m = mc + tid;
+        int64_t s0 = 0, len = 0;
+        if (m < m1) {
+            const int32_t x = member_idx[m];
+            s0 = sptr[x];
+            len = sptr[x + 1] - s0;
+        }
+        int64_t tot;
+        const int64_t off = block_excl_scan<EP_THREADS>(len, &tot, sh_scan);
+        sh_off[tid] = off;
+        sh_s0[tid] = s0;
+        __syncthreads();
+        const int nm = (int)min<int64_t>(EP_THREADS, m1 - mc);
+        for (int64_t e = tid; e < tot; e += EP_THREADS) {
+            int lo = 0, hi = nm - 1;                            // last member with offset <= e
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (sh_off[mid] <= e) lo = mid;
+                else hi = mid - 1;
+            }
+            const int32_t j = slist[sh_s0[lo] + (e - sh_off[lo])];
+            if (j > i) visit(j);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(EP_THREADS) void k_edge_pass(int mode, const int32_t *rows, int64_t L,
+                                                          const int64_t *seg, int nseg, const int64_t *row_ptr,
                                                           const int32_t *member_idx, const int64_t *sptr,
-                                                          const int32_t *slist, int64_t *deg,
-                                                          const int64_t *eptr, int32_t *edges)
+                                                          const int32_t *slist, int64_t *deg, const int64_t *eptr,
+                                                          int32_t *edges)
 {
     __shared__ int32_t buf[EP_CAP];
     __shared__ unsigned long long bits[EP_WORDS];
-    __shared__ int sh_cnt, sh_min, sh_max;
+    __shared__ int sh_cnt;
     __shared__ int64_t sh_scan[EP_THREADS / 64];
+    __shared__ int64_t sh_off[EP_THREADS], sh_s0[EP_THREADS];
     const int32_t i = rows ? rows[blockIdx.x] : (int32_t)blockIdx.x;
     const int64_t m0 = row_ptr[i], m1 = row_ptr[i + 1];
-    if (threadIdx.x == 0) {
-        sh_cnt = 0;
-        sh_min = INT_MAX;
-        sh_max = -1;
-    }
-    __syncthreads();
-    // pass 1: size and range of the union (with repeats)
-    {
-        int c = 0, mn = INT_MAX, mx = -1;
-        for (int64_t m = m0 + threadIdx.x; m < m1; m += EP_THREADS) {
-            const int32_t x = member_idx[m];
-            for (int64_t q = sptr[x]; q < sptr[x + 1]; ++q) {
-                const int32_t j = slist[q];
-                if (j > i) {
-                    ++c;
-                    mn = min(mn, j);
-                    mx = max(mx, j);
-                }
-            }
+    const int tid = (int)threadIdx.x;
+    // neighbours of row i lie in its segment [seg[c], seg[c + 1]) (a batch's
+    // chain), or anywhere below L
+    int64_t jend = L;
+    if (nseg > 0) {
+        int lo = 0, hi = nseg - 1;                                  // last c with seg[c] <= i
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (seg[mid] <= i) lo = mid;
+            else hi = mid - 1;
         }
-        if (c) {
-            atomicAdd(&sh_cnt, c);
-            atomicMin(&sh_min, mn);
-            atomicMax(&sh_max, mx);
-        }
+        jend = seg[lo + 1];
     }
-    __syncthreads();
-    const int total = sh_cnt;
+    // upper bound of the union (with repeats and entries <= i) from the list lengths
+    int64_t ub = 0;
+    for (int64_t m = m0 + tid; m < m1; m += EP_THREADS) {
+        const int32_t x = member_idx[m];
+        ub += sptr[x + 1] - sptr[x];
+    }
+    int64_t bound;
+    (void)block_excl_scan<EP_THREADS>(ub, &bound, sh_scan);
     const int64_t out0 = (mode == 1) ? eptr[i] : 0;
-    if (total == 0) {
-        if (mode == 0 && threadIdx.x == 0) deg[i] = 0;
-        return;
-    }
-    if (total <= EP_CAP) {
-        // gather, bitonic sort, keep first of each run
-        if (threadIdx.x == 0) sh_cnt = 0;
+    if (bound <= EP_CAP) {
+        // gather, bitonic sort, keep the first of each run
+        if (tid == 0) sh_cnt = 0;
         __syncthreads();
-        for (int64_t m = m0 + threadIdx.x; m < m1; m += EP_THREADS) {
-            const int32_t x = member_idx[m];
-            for (int64_t q = sptr[x]; q < sptr[x + 1]; ++q) {
-                const int32_t j = slist[q];
-                if (j > i) buf[atomicAdd(&sh_cnt, 1)] = j;
-            }
+        walk_union(i, m0, m1, member_idx, sptr, slist, sh_off, sh_s0, sh_scan,
+                   [&](int32_t j) { buf[atomicAdd(&sh_cnt, 1)] = j; });
+        const int total = sh_cnt;
+        if (total == 0) {
+            if (mode == 0 && tid == 0) deg[i] = 0;
+            return;
         }
         int P2 = 2;
         while (P2 < total) P2 <<= 1;
-        for (int t = total + threadIdx.x; t < P2; t += EP_THREADS) buf[t] = INT_MAX;
+        for (int t = total + tid; t < P2; t += EP_THREADS) buf[t] = INT_MAX;
         __syncthreads();
         for (int k = 2; k <= P2; k <<= 1) {
             for (int jj = k >> 1; jj > 0; jj >>= 1) {
-                for (int t = threadIdx.x; t < P2; t += EP_THREADS) {
+                for (int t = tid; t < P2; t += EP_THREADS) {
                     const int u = t ^ jj;
                     if (u > t) {
                         const int32_t a = buf[t], b = buf[u];
@@ -200,13 +231,13 @@ __global__ __launch_bounds__(EP_THREADS) void k_edge_pass(int mode, const int32_
         }
         // each thread owns a contiguous slice so positions follow the sorted order
         const int per = (total + EP_THREADS - 1) / EP_THREADS;
-        const int t0 = threadIdx.x * per;
+        const int t0 = tid * per;
         int64_t mine = 0;
         for (int t = t0; t < t0 + per && t < total; ++t) mine += (t == 0 || buf[t] != buf[t - 1]);
         int64_t uniq;
         int64_t pos = block_excl_scan<EP_THREADS>(mine, &uniq, sh_scan);
         if (mode == 0) {
-            if (threadIdx.x == 0) deg[i] = uniq;
+            if (tid == 0) deg[i] = uniq;
         } else {
             for (int t = t0; t < t0 + per && t < total; ++t) {
                 if (t == 0 || buf[t] != buf[t - 1]) {
@@ -218,25 +249,19 @@ __global__ __launch_bounds__(EP_THREADS) void k_edge_pass(int mode, const int32_
         }
         return;
     }
-    // bitmap over [jmin, jmax] in chunks of EP_WORDS * 64 landmarks
-    const int jmin = sh_min, jmax = sh_max;
+    // bitmap over j in (i, jend) in chunks of EP_WORDS * 64 landmarks
     int64_t written = 0;
-    for (int64_t base = jmin; base <= jmax; base += (int64_t)EP_WORDS * 64) {
-        const int64_t span = min((int64_t)EP_WORDS * 64, (int64_t)jmax - base + 1);
+    for (int64_t base = (int64_t)i + 1; base < jend; base += (int64_t)EP_WORDS * 64) {
+        const int64_t span = min((int64_t)EP_WORDS * 64, jend - base);
         const int nwords = (int)((span + 63) >> 6);
-        for (int t = threadIdx.x; t < nwords; t += EP_THREADS) bits[t] = 0ull;
+        for (int t = tid; t < nwords; t += EP_THREADS) bits[t] = 0ull;
         __syncthreads();
-        for (int64_t m = m0 + threadIdx.x; m < m1; m += EP_THREADS) {
-            const int32_t x = member_idx[m];
-            for (int64_t q = sptr[x]; q < sptr[x + 1]; ++q) {
-                const int64_t j = slist[q];
-                if (j > i && j >= base && j < base + span)
-                    atomicOr(&bits[(j - base) >> 6], 1ull << ((j - base) & 63));
-            }
-        }
-        __syncthreads();
+        walk_union(i, m0, m1, member_idx, sptr, slist, sh_off, sh_s0, sh_scan, [&](int32_t j) {
+            const int64_t r = (int64_t)j - base;
+            if (r >= 0 && r < span) atomicOr(&bits[r >> 6], 1ull << (r & 63));
+        });
         const int per = (nwords + EP_THREADS - 1) / EP_THREADS;
-        const int w0 = threadIdx.x * per;
+        const int w0 = tid * per;
         int64_t mine = 0;
         for (int w = w0; w < w0 + per && w < nwords; ++w) mine += __popcll(bits[w]);
         int64_t chunk_total;
@@ -256,16 +281,16 @@ __global__ __launch_bounds__(EP_THREADS) void k_edge_pass(int mode, const int32_
         written += chunk_total;
         __syncthreads();
     }
-    if (mode == 0 && threadIdx.x == 0) deg[i] = written;
+    if (mode == 0 && tid == 0) deg[i] = written;
 }
 
-hipError_t launch_edge_pass(int mode, int64_t nrows, const int32_t *rows, const int64_t *row_ptr,
-                            const int32_t *member_idx, const int64_t *sptr, const int32_t *slist, int64_t *deg,
-                            const int64_t *eptr, int32_t *edges, hipStream_t s)
+hipError_t launch_edge_pass(int mode, int64_t nrows, const int32_t *rows, int64_t L, const int64_t *seg, int nseg,
+                            const int64_t *row_ptr, const int32_t *member_idx, const int64_t *sptr,
+                            const int32_t *slist, int64_t *deg, const int64_t *eptr, int32_t *edges, hipStream_t s)
 {
     if (nrows <= 0) return hipSuccess;
-    k_edge_pass<<<(unsigned)nrows, EP_THREADS, 0, s>>>(mode, rows, row_ptr, member_idx, sptr, slist, deg, eptr,
-                                                       edges);
+    k_edge_pass<<<(unsigned)nrows, EP_THREADS, 0, s>>>(mode, rows, L, seg, nseg, row_ptr, member_idx, sptr, slist,
+                                                       deg, eptr, edges);
     return hipGetLastError();
 }
 

@@ -180,22 +180,15 @@ __device__ void block_open(const ChainTask &T, unsigned char *lds)
     }
 }
 
-__device__ __forceinline__ uint64_t wave_or64(uint64_t x)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o, 64);
-    return x;
-}
-
 // Accept the opened block of chain T in rank order, by rounds: a candidate
 // without any earlier conflict (rowflag 0) is accepted at once; otherwise it
 // is rejected as soon as one of its earlier conflicts is accepted, and
 // accepted once all of them are rejected.  Decisions never change, so a stale
 // view only delays one; the earliest undecided candidate always has all its
 // conflicts decided, so every round decides at least one.  The result equals
-// the sequential scan.  Flagged candidates are listed first; in a round one
-// wave takes one flagged row, lane w reading conflict words w, w + 64
-// (coalesced loads).  The accepted ranks go to A (the range pass's list), the
+// the sequential scan.  Each thread takes a contiguous run of candidates for
+// the listing and the compaction (one block scan each); in a round one wave
+// takes one flagged row, lane w reading conflict words w, w + 64 (coalesced).  The accepted ranks go to A (the range pass's list), the
 // landmark list (original indices) and lm_rank at ordinal st->L, and the
 // block is recorded in blog[(st->blocks - 1) % kBlockLogSize].
 template <int NT>
@@ -221,18 +214,19 @@ __device__ void block_accept(const ChainTask &T, unsigned char *lds)
     uint64_t *islm = T.settle ? T.islm : nullptr;
     for (int t = tid; t < MAX_B / 64; t += NT) acc[t] = rej[t] = 0ull;
     __syncthreads();
-    // rows with no earlier conflict are accepted; the flagged ones are listed in rank order
-    int F = 0;
-    for (int j0 = 0; j0 < nc; j0 += NT) {
-        const int j = j0 + tid;
-        const bool fl = j < nc && T.rowflag[j] != 0;
-        const uint64_t okm = __ballot(j < nc && !fl);
-        if (lane == 0) acc[(j0 >> 6) + wid] = okm;               // the wave's 64 rows are one word
-        int tot;
-        const int pre = block_excl_scan<NT>((int)fl, &tot, sh_scan);
-        if (fl) flist[F + pre] = (int16_t)j;
-        F += tot;
+    // rows with no earlier conflict are accepted; the flagged ones are listed in
+    // rank order.  Thread t takes the contiguous run [t * per, (t + 1) * per).
+    const int per = (nc + NT - 1) / NT;
+    const int j0 = tid * per, j1 = min(nc, j0 + per);
+    int nfl = 0;
+    for (int j = j0; j < j1; ++j) {
+        if (T.rowflag[j] != 0) ++nfl;
+        else atomicOr(&acc[j >> 6], 1ull << (j & 63));
     }
+    int F;
+    int pre = block_excl_scan<NT>(nfl, &F, sh_scan);
+    for (int j = j0; j < j1 && nfl > 0; ++j)
+        if (T.rowflag[j] != 0) flist[pre++] = (int16_t)j;
     __syncthreads();
     unsigned long long rounds = 0;
     while (F > 0) {                                              // uniform
@@ -275,35 +269,31 @@ __device__ void block_accept(const ChainTask &T, unsigned char *lds)
             break;
         }
     }
-    // the accepted candidates, compacted in rank order
-    int total = 0;
-    for (int j0 = 0; j0 < nc; j0 += NT) {
-        const int j = j0 + tid;
-        const bool take = j < nc && ((acc[j >> 6] >> (j & 63)) & 1ull);
-        int tot;
-        const int pre = block_excl_scan<NT>((int)take, &tot, sh_scan);
-        int32_t r = 0;
-        if (take) {
-            r = T.cand[j];
-            const int pos = total + pre;
-            T.A[pos] = r;
-            T.landmarks[L0 + pos] = T.perm ? T.perm[r] : r;
-            T.lm_rank[L0 + pos] = r;
-        }
-        if (islm) {                                              // one atomic per distinct word of the wave
-            uint64_t pend = __ballot(take);
-            while (pend) {
-                const int leader = __ffsll((unsigned long long)pend) - 1;
-                const int w = __shfl(r >> 6, leader, 64);
-                const bool mine = take && (r >> 6) == w;
-                const uint64_t same = __ballot(mine);
-                const uint64_t bits = wave_or64(mine ? (1ull << (r & 63)) : 0ull);
-                if (lane == leader) atomicOr((unsigned long long *)&islm[w], (unsigned long long)bits);
-                pend &= ~same;
+    // the accepted candidates, compacted in rank order (each thread its run);
+    // landmark bits are merged per bitmap word before one atomic
+    int mine = 0;
+    for (int j = j0; j < j1; ++j) mine += (int)((acc[j >> 6] >> (j & 63)) & 1ull);
+    int total;
+    int pos = block_excl_scan<NT>(mine, &total, sh_scan);
+    int64_t word = -1;
+    unsigned long long bits = 0;
+    for (int j = j0; j < j1 && mine > 0; ++j) {
+        if (!((acc[j >> 6] >> (j & 63)) & 1ull)) continue;
+        const int32_t r = T.cand[j];
+        T.A[pos] = r;
+        T.landmarks[L0 + pos] = T.perm ? T.perm[r] : r;
+        T.lm_rank[L0 + pos] = r;
+        ++pos;
+        if (islm) {
+            if ((r >> 6) != word) {
+                if (bits) atomicOr((unsigned long long *)&islm[word], bits);
+                word = r >> 6;
+                bits = 0;
             }
+            bits |= 1ull << (r & 63);
         }
-        total += tot;
     }
+    if (islm && bits) atomicOr((unsigned long long *)&islm[word], bits);
     if (tid == 0) {
         st->L0 = L0;
         st->na = total;

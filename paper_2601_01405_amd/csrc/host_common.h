@@ -22,6 +22,7 @@
 #include "bm_internal.h"
 #include "bounds.h"
 #include "kernels.h"
+#include "tuned_blocks.h"
 
 namespace bm {
 namespace host {
@@ -266,6 +267,7 @@ struct GraphRunner {
 };
 constexpr int kGraphBlocks = 8;                     // greedy blocks per captured graph
 constexpr int64_t kGraphMaxPoints = 1 << 17;        // single builds replay graphs below this size
+constexpr int64_t kProbePoints = 1 << 17;           // single builds from this size sample ball sizes
 
 inline bm_result *new_result()
 {
@@ -302,13 +304,28 @@ inline int device_flags(int dev, hipStream_t s)
     return flags;
 }
 
-inline int auto_block(int64_t n, int path)
+// Candidate block size when the options leave it automatic: the measured
+// table (tuned_blocks.h) for the matrix-core paths, by cloud size otherwise.
+inline int32_t tuned_block(int64_t n, int32_t d, bool batch)
+{
+    const TunedBlock *best = nullptr;
+    for (const TunedBlock &t : kTunedBlocks) {
+        if (n < t.n_min || d > t.d_max) continue;
+        if (!best || t.n_min > best->n_min || (t.n_min == best->n_min && t.d_max < best->d_max)) best = &t;
+    }
+    if (!best) return 0;
+    const int32_t B = batch ? best->batch : best->single;
+    return std::min<int32_t>(std::max<int32_t>(B, 1), 8192);
+}
+
+inline int auto_block(int64_t n, int32_t d, int path)
 {
     if (path == BM_PATH_FP32) {
         if (n >= (1 << 17)) return 1024;
         if (n >= (1 << 13)) return 256;
         return 64;
     }
+    if (const int32_t B = tuned_block(n, d, false)) return B;
     if (n >= (1 << 17)) return 8192;
     if (n >= (1 << 13)) return 256;
     return 64;
@@ -383,14 +400,18 @@ inline void release_mfma(Device &dev, const MfmaArgs &ma)
     dev.release((void *)ma.cinit);
 }
 
-// Fraction of landmark-point pairs a filter leaves to the FP64 recheck at
-// radius e2: one range pass of up to 512 landmarks at evenly spaced ranks
-// against every point, keeping no membership.
-inline double sample_band_rate(Device &dev, const PointsView &P, const MfmaArgs &ma, double e2)
+// One range pass of m landmarks at evenly spaced ranks against every point,
+// keeping no membership: the fraction of pairs the filter leaves to the FP64
+// recheck, and the mean number of members of a landmark's ball.
+struct SampleStats {
+    double band_rate = 0.0, ball_mean = 0.0;
+};
+inline SampleStats sample_pass(Device &dev, const PointsView &P, const MfmaArgs &ma, double e2, int m_max)
 {
+    SampleStats out;
     const int64_t n = P.n;
-    const int m = (int)std::min<int64_t>(n, 512);
-    if (m <= 0) return 0.0;
+    const int m = (int)std::min<int64_t>(n, m_max);
+    if (m <= 0) return out;
     std::vector<int32_t> ranks((size_t)m);
     for (int j = 0; j < m; ++j) ranks[(size_t)j] = (int32_t)(((int64_t)j * n) / m);
     int32_t *A = dev.alloc<int32_t>((size_t)m);
@@ -410,10 +431,16 @@ inline double sample_band_rate(Device &dev, const PointsView &P, const MfmaArgs 
     range_grid(m, n, range_target_wg(), &t.NGW, &t.chunks);
     RangeTask *td = dev.alloc<RangeTask>(1);
     dev.upload(td, &t, sizeof t);
-    hip_ok(launch_range_tasks(td, nullptr, (int64_t)t.NGW * t.chunks, ma.kind, ma.S, false, dev.s), "band probe");
+    hip_ok(launch_range_tasks(td, nullptr, (int64_t)t.NGW * t.chunks, ma.kind, ma.S, false, dev.s), "sample pass");
     const GreedyState h = dev.fetch(st);
     for (void *ptr : {(void *)A, (void *)blk, (void *)st, (void *)none, (void *)td}) dev.release(ptr);
-    return (double)h.band / ((double)m * (double)n);
+    out.band_rate = (double)h.band / ((double)m * (double)n);
+    out.ball_mean = (double)h.nkeys / (double)m;
+    return out;
+}
+inline double sample_band_rate(Device &dev, const PointsView &P, const MfmaArgs &ma, double e2)
+{
+    return sample_pass(dev, P, ma, e2, 512).band_rate;
 }
 
 // The three-product split stops being almost free once its K passes 48 (below
@@ -502,11 +529,14 @@ inline void scan_into(Device &dev, const int64_t *in, int64_t *out, int64_t coun
 }
 
 // Edges (i, j), i < j, of rows that share a column, lexicographic, through the
-// transpose S(x); only rows with a column in another row are visited.  Returns
+// transpose S(x); only rows with a column in another row are visited.  seg (a
+// batch's chain offsets, nseg + 1 entries on the device) bounds each row's
+// neighbours to its chain.  Returns
 // E and sets *edges (2 E ints); if eptr_out, keeps the per-row edge offsets
 // (L + 1 entries, zeros for L <= 1 or M == 0).
 inline int64_t edges_of(Device &dev, const uint64_t *skeys, int64_t M, int64_t L, int64_t N, int32_t bn,
-                        const int64_t *row_ptr, const int32_t *midx, int32_t **edges, int64_t **eptr_out)
+                        const int64_t *row_ptr, const int32_t *midx, int32_t **edges, int64_t **eptr_out,
+                        const int64_t *seg = nullptr, int nseg = 0)
 {
     if (L <= 1 || M == 0) {
         *edges = dev.alloc<int32_t>(1);
@@ -528,13 +558,15 @@ inline int64_t edges_of(Device &dev, const uint64_t *skeys, int64_t M, int64_t L
     const int64_t nrows = (int64_t)dev.fetch(nrows_d);
     dev.release(flag);
     int64_t *deg = dev.zeros<int64_t>((size_t)L);
-    hip_ok(launch_edge_pass(0, nrows, rows, row_ptr, midx, sptr, slist, deg, nullptr, nullptr, dev.s), "edge count");
+    hip_ok(launch_edge_pass(0, nrows, rows, L, seg, nseg, row_ptr, midx, sptr, slist, deg, nullptr, nullptr, dev.s),
+           "edge count");
     int64_t *eptr = dev.alloc<int64_t>((size_t)L + 1);
     scan_into(dev, deg, eptr, L);
     const int64_t E = (int64_t)dev.fetch(eptr + L);
     *edges = dev.alloc<int32_t>((size_t)std::max<int64_t>(2 * E, 1));
     if (E > 0)
-        hip_ok(launch_edge_pass(1, nrows, rows, row_ptr, midx, sptr, slist, deg, eptr, *edges, dev.s), "edge emit");
+        hip_ok(launch_edge_pass(1, nrows, rows, L, seg, nseg, row_ptr, midx, sptr, slist, deg, eptr, *edges, dev.s),
+               "edge emit");
     dev.release(deg);
     dev.release(rows);
     dev.release(slist);

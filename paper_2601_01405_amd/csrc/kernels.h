@@ -85,11 +85,13 @@ hipError_t launch_fill_slists(const uint64_t *keys, int64_t M, int32_t bn, const
 // (|S(x)| > 1), from the sorted keys; flag[L] and *count must start at zero.
 hipError_t launch_edge_rows(const uint64_t *keys, int64_t M, int32_t bn, const int64_t *sptr, int64_t L, int *flag,
                             int32_t *list, unsigned long long *count, hipStream_t s);
-// Over the rows rows[0..nrows) (null: 0..nrows-1).  mode 0: deg[i] = number of
-// neighbours j > i;  mode 1: write them at eptr[i].
-hipError_t launch_edge_pass(int mode, int64_t nrows, const int32_t *rows, const int64_t *row_ptr,
-                            const int32_t *member_idx, const int64_t *sptr, const int32_t *slist, int64_t *deg,
-                            const int64_t *eptr, int32_t *edges, hipStream_t s);
+// Over the rows rows[0..nrows) (null: 0..nrows-1) of L rows.  mode 0: deg[i] =
+// number of neighbours j > i;  mode 1: write them at eptr[i].  seg[0..nseg]
+// (device, may be null) splits the rows into segments that share no column
+// (the chains of a batch), which bounds the neighbours of a row.
+hipError_t launch_edge_pass(int mode, int64_t nrows, const int32_t *rows, int64_t L, const int64_t *seg, int nseg,
+                            const int64_t *row_ptr, const int32_t *member_idx, const int64_t *sptr,
+                            const int32_t *slist, int64_t *deg, const int64_t *eptr, int32_t *edges, hipStream_t s);
 
 // ---- batches (batch.hip) ---------------------------------------------------------------------
 // Sorted chain-tagged keys (chain << (bl + bn) | ordinal << bn | index) into the

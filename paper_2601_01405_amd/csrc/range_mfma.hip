@@ -271,15 +271,32 @@ __device__ void range_wg_exit(const RangeTask &T, KernelClock *clk, unsigned cha
 }
 
 // LDS of a range workgroup: the double-buffered stages, the accumulator
-// starts and norm bounds, then one band queue of kQueue entries per wave.
-constexpr int kQueue = 512;
+// starts and norm bounds, one band queue per wave (queue_cap entries), and a
+// key stage: members are appended there with LDS atomics and written out in
+// chunks at stage barriers, one global atomic per chunk, so that the key
+// counter (one per build, or per batch) is not hit once per wave and panel.
+constexpr int kKeyStage = 2048;
+constexpr size_t kLdsBudget = 160 * 1024;                          // LDS of one workgroup on gfx950
 __host__ __device__ constexpr size_t queue_offset(int S, int TPS)
 {
     return (size_t)2 * TPS * (S * 64 * 16 + 24 * 16) + 2 * RM_THREADS * sizeof(float);
 }
+// Band-queue entries per wave: what the stages and the key stage leave of the
+// budget (1 KB kept for the kernel's own variables), 64 to 1024, a multiple of 64.
+__host__ __device__ constexpr int queue_cap(int S, int TPS)
+{
+    const size_t used = queue_offset(S, TPS) + (size_t)kKeyStage * 8 + 16 + 1024;
+    const size_t q = used < kLdsBudget ? (kLdsBudget - used) / ((size_t)RM_WAVES * 8) : 0;
+    const size_t c = q > 1024 ? 1024 : q;
+    return (int)(c < 64 ? 64 : (c / 64) * 64);
+}
+__host__ __device__ constexpr size_t key_stage_offset(int S, int TPS)
+{
+    return queue_offset(S, TPS) + (size_t)RM_WAVES * queue_cap(S, TPS) * 8;
+}
 __host__ __device__ constexpr size_t range_lds_bytes(int S, int TPS)
 {
-    return queue_offset(S, TPS) + (size_t)RM_WAVES * kQueue * 8;
+    return key_stage_offset(S, TPS) + (size_t)kKeyStage * 8 + 16;
 }
 
 template <int KS, bool F16, bool CONFLICT, bool CHUNKED>
@@ -351,6 +368,17 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
         }
         sC[tid] = cv;
         sN[tid] = nv;
+    }
+    uint64_t *kst = (uint64_t *)(smem + key_stage_offset(CHUNKED ? a.S : KS, TPS));
+    int *kst_n = (int *)(kst + kKeyStage);
+    // kst_seen[s & 1]: the stage count as thread 0 saw it early in stage s.  A
+    // flush in stage s is decided on kst_seen[(s - 1) & 1], which no one writes
+    // during stage s, so every wave takes the same decision.
+    __shared__ int kst_seen[2];
+    __shared__ unsigned long long sh_kbase;
+    if (!CONFLICT && tid == 0) {
+        *kst_n = 0;
+        kst_seen[0] = kst_seen[1] = 0;
     }
     __syncthreads();
 
@@ -466,7 +494,8 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
     // row loads overlap instead of stalling the wave once per pair (a full
     // queue rechecks in place).  Entry: landmark index in the pass << 40 |
     // settled flag << 32 | point (rank or settled entry).
-    uint64_t *bq = (uint64_t *)(smem + queue_offset(CHUNKED ? a.S : KS, TPS)) + wid * kQueue;
+    const int QCAP = queue_cap(CHUNKED ? a.S : KS, TPS);
+    uint64_t *bq = (uint64_t *)(smem + queue_offset(CHUNKED ? a.S : KS, TPS)) + wid * QCAP;
     int qn = 0;                                                    // wave-uniform
     auto flush_queue = [&]() {
         for (int q0 = 0; q0 < qn; q0 += 64) {
@@ -495,16 +524,39 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
         }
         qn = 0;
     };
+    // Write the key stage out.  Every thread of the workgroup calls it at the
+    // same point; after the first barrier no wave appends, so the count is the
+    // same for all.
+    auto flush_keys = [&]() {
+        __syncthreads();
+        const int kn = min(*kst_n, kKeyStage);
+        if (kn == 0) return;                                        // workgroup-uniform
+        if (tid == 0) sh_kbase = atomicAdd(o.nkeys, (unsigned long long)kn);
+        __syncthreads();
+        const unsigned long long kb = sh_kbase;
+        for (int i = tid; i < kn; i += RM_THREADS)
+            if (kb + i < o.cap) o.keys[kb + i] = kst[i];
+        __syncthreads();                                            // every copy has read the stage
+        if (tid == 0) *kst_n = 0;
+        __syncthreads();
+    };
     // Let the setup loads (A operands, accumulator starts) land before the loop,
     // so the only loads in flight inside it are the next stage's staging loads
     // and the waitcnt pass need not wait for them before the matrix ops.
     __builtin_amdgcn_s_waitcnt(0);
     // One stage: store its staged loads to LDS buffer `buf`, start the loads of
     // the stage two ahead into the same registers, multiply the stage.
+    int si = 0;                                                      // stage index (uniform)
     auto run_stage = [&](int ts, int buf, u32x4 (&pre)[OPS], u32x4 &pre_t) {
         lstore(buf, pre, pre_t);
         __syncthreads();
         gload(ts + 2 * TPS, pre, pre_t);
+        if (!CONFLICT) {
+            const bool flush = kst_seen[(si + 1) & 1] >= kKeyStage / 2;   // slot (si - 1) & 1: uniform
+            if (flush) flush_keys();
+            if (tid == 0) kst_seen[si & 1] = flush ? 0 : *kst_n;
+            ++si;
+        }
         if (!live) return;
       for (int tt = 0; tt < TPS; ++tt) {
         const int t = ts + tt;
@@ -587,7 +639,7 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
                 band += (unsigned long long)bc;
                 const int bincl = wave_incl_scan(bc);
                 const int btot = __shfl(bincl, 63, 64);
-                if (!CONFLICT && btot > 0 && qn + btot <= kQueue) {
+                if (!CONFLICT && btot > 0 && qn + btot <= QCAP) {
                     // queue them (rechecked after the loop, lane-parallel)
                     int pos = qn + bincl - bc;
                     while (bnd) {
@@ -628,21 +680,29 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
                 }
                 continue;
             }
-            // append this lane's members with one atomic per wave
+            // append this lane's members to the key stage (one LDS atomic per
+            // wave); what does not fit goes to the key buffer directly
             const int cnt = __popc(mem);
             if (!__ballot(cnt != 0)) continue;
             const int incl = wave_incl_scan(cnt);
             const int total = __shfl(incl, 63, 64);
-            unsigned long long base = 0;
-            if (lane == 0) base = atomicAdd(o.nkeys, (unsigned long long)total);
-            base = __shfl(base, 0, 64) + (unsigned long long)(incl - cnt);
+            int lbase = 0;
+            if (lane == 0) lbase = atomicAdd(kst_n, total);
+            lbase = __shfl(lbase, 0, 64);
+            const int spill0 = max(lbase, kKeyStage);                  // first slot past the stage
+            const int nspill = lbase + total - spill0;
+            unsigned long long gbase = 0;
+            if (nspill > 0 && lane == 0) gbase = atomicAdd(o.nkeys, (unsigned long long)nspill);
+            gbase = __shfl(gbase, 0, 64);
             cov |= cnt != 0;
+            int pos = lbase + incl - cnt;
             while (mem) {
                 const int i = __builtin_ctz(mem);
                 mem &= mem - 1;
-                if (base < o.cap)
-                    o.keys[base] = ((uint64_t)(ord0 + abase + acc_row(i, half)) << o.bn) | (uint64_t)xo | o.tag;
-                ++base;
+                const uint64_t key = ((uint64_t)(ord0 + abase + acc_row(i, half)) << o.bn) | (uint64_t)xo | o.tag;
+                if (pos < kKeyStage) kst[pos] = key;
+                else if (gbase + (pos - spill0) < o.cap) o.keys[gbase + (pos - spill0)] = key;
+                ++pos;
             }
         }
         if (!CONFLICT && slow && o.covered && t >= MT) {                 // wave-uniform
@@ -667,6 +727,7 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
     }
     if (ts < t1) run_stage(ts, 0, preA, pretA);
     if (!CONFLICT && live) flush_queue();
+    if (!CONFLICT) flush_keys();
     band = wave_sum(band);
     if (band && lane == 0 && o.st) atomicAdd(&o.st->band, band);
     range_wg_exit<CONFLICT>(T, clk, smem);
@@ -748,8 +809,10 @@ static hipError_t launch_ks(const RangeTask *tasks, const int32_t *task_of, int6
                             hipStream_t s, LaunchEvents ev)
 {
     constexpr int TPS = stage_tiles(CHUNKED, KS);
-    const size_t shmem = std::max(range_lds_bytes(S, TPS),
+    // a resolve uses neither the band queue nor the key stage
+    const size_t shmem = std::max(CONFLICT ? queue_offset(S, TPS) : range_lds_bytes(S, TPS),
                                   std::max(open_lds_bytes<RM_THREADS>(), accept_lds_bytes<RM_THREADS>()));
+    if (shmem + 1024 > kLdsBudget) return hipErrorInvalidValue;
     if (ev.start || ev.stop)          // events attached to the dispatch (not capturable in a graph)
         hipExtLaunchKernelGGL(k_range_mfma<KS, F16, CONFLICT, CHUNKED>, dim3((unsigned)wgs), dim3(RM_THREADS),
                               (uint32_t)shmem, s, ev.start, ev.stop, 0, tasks, task_of, nch, ev.clock);
