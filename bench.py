@@ -48,6 +48,8 @@ def parse():
                     help="write a kernel-trace summary of a rocprofv3 database and exit")
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_DB", "WRITE_DB", "OUT"),
                     help="write the range pass's HBM traffic per launch from two rocprofv3 --pmc databases")
+    ap.add_argument("--summarize-sq", nargs=2, metavar=("DB", "OUT"),
+                    help="write the range pass's matrix-core use from a rocprofv3 --pmc run of the SQ counters")
     ap.add_argument("--command", default="", help="the profiled command, recorded in a summary")
     return ap.parse_args()
 
@@ -170,6 +172,41 @@ def summarize_traffic(fetch_db, write_db, out, command):
                   f"{counter.lower()}_bytes_per_launch = {res[counter]:.0f}"]
     lines += [f"kernel_source_sha256_16 = {kernel_hash()}",
               f"hbm_bytes_per_launch = {res['FETCH_SIZE'] + res['WRITE_SIZE']:.0f}"]
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+SQ_COUNTERS = ("SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE", "SQ_INSTS_MFMA", "SQ_INSTS_VALU", "SQ_INSTS_LDS",
+               "SQ_WAVES", "SQ_BUSY_CYCLES")
+
+
+def summarize_sq(db, out, command, durations_db=None):
+    """Matrix-core use of the range pass from one rocprofv3 --pmc run of the SQ
+    counters: per dispatch averages, and MFMA busy cycles over GPU-active cycles
+    of all 1024 SIMDs (rocprofv3's MfmaUtil definition)."""
+    lines = ["# Matrix-core use of the range pass (k_range_mfma, membership mode), rocprofv3 SQ counters",
+             f"# command: {command}",
+             "# values are per dispatch, averaged over the range-pass dispatches"]
+    avg = {}
+    for c in SQ_COUNTERS:
+        per = _dispatch_values(db, c)
+        v = [x for (name, _), x in per.items() if is_range_pass(name)]
+        if v:
+            avg[c] = sum(v) / len(v)
+            lines.append(f"{c.lower()}_per_dispatch = {avg[c]:.0f}")
+    if "SQ_VALU_MFMA_BUSY_CYCLES" in avg and avg.get("GRBM_GUI_ACTIVE"):
+        # the CSV sums GRBM_GUI_ACTIVE over the 8 XCDs (it reads about 8x the
+        # dispatch's duration in 2.4 GHz cycles); one XCD's count is the GPU's
+        # active time
+        active = avg["GRBM_GUI_ACTIVE"] / 8.0
+        util = avg["SQ_VALU_MFMA_BUSY_CYCLES"] / (active * 1024.0)
+        lines.append(f"gpu_active_cycles_per_dispatch = {active:.0f}   # GRBM_GUI_ACTIVE / 8 XCDs")
+        lines.append(f"mfma_busy_fraction = {util:.4f}   "
+                     "# SQ_VALU_MFMA_BUSY_CYCLES / (active cycles x 1024 SIMDs)")
+    if "SQ_INSTS_MFMA" in avg and "SQ_INSTS_VALU" in avg:
+        lines.append(f"valu_insts_per_mfma = {avg['SQ_INSTS_VALU'] / max(avg['SQ_INSTS_MFMA'], 1.0):.2f}")
+    lines.append(f"kernel_source_sha256_16 = {kernel_hash()}")
     with open(out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -298,6 +335,9 @@ def main():
         return
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace, args.command)
+        return
+    if args.summarize_sq:
+        summarize_sq(*args.summarize_sq, args.command)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
