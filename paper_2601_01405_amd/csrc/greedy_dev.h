@@ -215,18 +215,42 @@ __device__ void block_accept(const ChainTask &T, unsigned char *lds)
     for (int t = tid; t < MAX_B / 64; t += NT) acc[t] = rej[t] = 0ull;
     __syncthreads();
     // rows with no earlier conflict are accepted; the flagged ones are listed in
-    // rank order.  Thread t takes the contiguous run [t * per, (t + 1) * per).
-    const int per = (nc + NT - 1) / NT;
+    // rank order.  Thread t takes the contiguous run [t * per, (t + 1) * per),
+    // its row flags and ranks loaded up front (independent loads).
+    constexpr int RUN = MAX_B / NT;
+    const int per = (nc + NT - 1) / NT;                          // <= RUN
     const int j0 = tid * per, j1 = min(nc, j0 + per);
-    int nfl = 0;
-    for (int j = j0; j < j1; ++j) {
-        if (T.rowflag[j] != 0) ++nfl;
-        else atomicOr(&acc[j >> 6], 1ull << (j & 63));
+    int32_t rank[RUN];
+    uint32_t flagged = 0, inrun = 0;
+#pragma unroll
+    for (int k = 0; k < RUN; ++k) {
+        const int j = j0 + k;
+        const bool in = j < j1;
+        const int f = in ? T.rowflag[j] : 0;
+        rank[k] = in ? T.cand[j] : 0;
+        if (in) inrun |= 1u << k;
+        if (f) flagged |= 1u << k;
     }
+    {
+        // the run spans at most two bitmap words: one LDS atomic per word
+        uint32_t ok = inrun & ~flagged;
+        while (ok) {
+            const int k = __builtin_ctz(ok);
+            const int w = (j0 + k) >> 6;
+            unsigned long long bits = 0;
+            while (ok) {
+                const int kk = __builtin_ctz(ok);
+                if (((j0 + kk) >> 6) != w) break;
+                bits |= 1ull << ((j0 + kk) & 63);
+                ok &= ok - 1;
+            }
+            atomicOr(&acc[w], bits);
+        }
+    }
+    const int nfl = __popc(flagged);
     int F;
     int pre = block_excl_scan<NT>(nfl, &F, sh_scan);
-    for (int j = j0; j < j1 && nfl > 0; ++j)
-        if (T.rowflag[j] != 0) flist[pre++] = (int16_t)j;
+    for (uint32_t fl = flagged; fl; fl &= fl - 1) flist[pre++] = (int16_t)(j0 + __builtin_ctz(fl));
     __syncthreads();
     unsigned long long rounds = 0;
     while (F > 0) {                                              // uniform
@@ -271,17 +295,24 @@ __device__ void block_accept(const ChainTask &T, unsigned char *lds)
     }
     // the accepted candidates, compacted in rank order (each thread its run);
     // landmark bits are merged per bitmap word before one atomic
-    int mine = 0;
-    for (int j = j0; j < j1; ++j) mine += (int)((acc[j >> 6] >> (j & 63)) & 1ull);
+    uint32_t took = 0;
+#pragma unroll
+    for (int k = 0; k < RUN; ++k)
+        if (((inrun >> k) & 1u) && ((acc[(j0 + k) >> 6] >> ((j0 + k) & 63)) & 1ull)) took |= 1u << k;
+    int32_t orig[RUN];
+#pragma unroll
+    for (int k = 0; k < RUN; ++k) orig[k] = ((took >> k) & 1u) && T.perm ? T.perm[rank[k]] : rank[k];
+    const int mine = __popc(took);
     int total;
     int pos = block_excl_scan<NT>(mine, &total, sh_scan);
     int64_t word = -1;
     unsigned long long bits = 0;
-    for (int j = j0; j < j1 && mine > 0; ++j) {
-        if (!((acc[j >> 6] >> (j & 63)) & 1ull)) continue;
-        const int32_t r = T.cand[j];
+#pragma unroll
+    for (int k = 0; k < RUN; ++k) {
+        if (!((took >> k) & 1u)) continue;
+        const int32_t r = rank[k];
         T.A[pos] = r;
-        T.landmarks[L0 + pos] = T.perm ? T.perm[r] : r;
+        T.landmarks[L0 + pos] = orig[k];
         T.lm_rank[L0 + pos] = r;
         ++pos;
         if (islm) {

@@ -619,7 +619,9 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
             const int64_t p = tr * 32 + col;                             // settled entry or rank
             const bool pv = stl ? p < msz : p < n;
             uint32_t mem = 0;
-            const int64_t xo = !pv ? 0 : CONFLICT ? orig_index(P, A[p]) : stl ? (int64_t)sd.idx[p] : orig_index(P, p);
+            // the point's original index: for the keys (range pass), or only when a
+            // band pair needs the FP64 recheck (resolve)
+            const int64_t xo = (!pv || CONFLICT) ? 0 : stl ? (int64_t)sd.idx[p] : orig_index(P, p);
             if (a.refine) {
                 const float u = thr[col] - aw[pi];
                 const float v = thr[32 + col] + aw[pi];
@@ -650,14 +652,15 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
                     }
                     qn += btot;
                     __builtin_amdgcn_wave_barrier();
-                } else {
+                } else if (bnd) {
                     // the queue is full (or a resolve): recheck in place
+                    const int64_t xr = CONFLICT ? orig_index(P, A[p]) : xo;
                     while (bnd) {
                         const int i = __builtin_ctz(bnd);
                         bnd &= bnd - 1;
                         const int ai = abase + acc_row(i, half);
                         const int32_t lr = A ? A[ai] : ai;
-                        if (exact_member(P, orig_index(P, lr), xo, e2)) mem |= 1u << i;
+                        if (exact_member(P, orig_index(P, lr), xr, e2)) mem |= 1u << i;
                     }
                 }
             } else {
