@@ -212,7 +212,9 @@ __device__ __forceinline__ int acc_row(int i, int half) { return 8 * (i >> 2) + 
 // mode is the candidate-block resolve: landmarks and points are both the
 // block's candidates (rank A[j] for candidate j, read in place), and the
 // output is C32[j * stride + p] = the bits r of rows i = 32 p + r < j whose
-// ball holds candidate j, plus rowflag[j] = 1 when any bit is set.
+// ball holds candidate j, for the panels p with 32 p < j (the accept masks or
+// skips the others), plus rowflag[j] = 1 when any bit is set.  Tiles that lie
+// wholly above the diagonal are skipped.
 //
 // Point space of a MEMBERS pass: tiles [0, MT) are the settled list (entries
 // < m valid), then rank tiles from rlo / 32 to the end.  A CONFLICT pass has
@@ -349,7 +351,9 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
     const int tpc = (CT + chunks - 1) / chunks;
     const int t0 = c * tpc;
     const int t1 = min(CT, t0 + tpc);
-    if (t0 >= t1) {                                                // workgroup-uniform
+    // a resolve needs rows i < j only: no candidate of the chunk lies past
+    // the group's first row, so every word it could write is never read
+    if (t0 >= t1 || (CONFLICT && g * RM_THREADS >= t1 * 32 - 1)) {  // workgroup-uniform
         range_wg_exit<CONFLICT>(T, clk, smem);
         return;
     }
@@ -561,6 +565,8 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
       for (int tt = 0; tt < TPS; ++tt) {
         const int t = ts + tt;
         if (t >= t1) break;                                             // wave-uniform
+        // resolve: the wave's rows all follow the tile's candidates (i >= j)
+        if (CONFLICT && pbase * 32 >= t * 32 + 31) continue;            // wave-uniform
         const int sb = buf * buf_vecs + tt * tile_vecs;                 // this tile's operands in LDS
         const float *thr = (const float *)(sT + buf * THV + tt * 24);   // and thresholds
         f32x16 acc[RM_MP];
@@ -598,7 +604,7 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
             const int abase = (pbase + pi) * 32;
             if (abase >= na) break;                                      // wave-uniform
             const f32x16 av = acc[pi];
-            if (!CONFLICT) {
+            {
                 // fast path: is any pair of the 32x32 tile possibly a member?
                 // u, v: conservative thresholds for this point and panel (U, V and aw
                 // carry the slack for these two roundings); +inf for padding points
@@ -611,7 +617,16 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
                 m = fmaxf(fmaxf(m, av[11]), av[12]);
                 m = fmaxf(fmaxf(m, av[13]), av[14]);
                 m = fmaxf(m, av[15]);
-                if (!__ballot(!(m <= cut))) continue;
+                if (!__ballot(!(m <= cut))) {
+                    if (CONFLICT) {
+                        // no pair of the tile conflicts: a zero word for every
+                        // candidate past the panel's first row (the words a row
+                        // reads; the others are masked or never read)
+                        const int64_t p = (int64_t)t * 32 + col;
+                        if (half == 0 && p < n && abase < p) T.C32[p * T.c32_stride + (pbase + pi)] = 0u;
+                    }
+                    continue;
+                }
             }
             slow = true;
             const bool stl = t < MT;                                     // wave-uniform
@@ -677,7 +692,7 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
                 for (int i = 0; i < 16; ++i)
                     if ((mem >> i) & 1u) w |= 1u << acc_row(i, half);
                 w |= __shfl_xor(w, 32, 64);
-                if (half == 0 && pv) {
+                if (half == 0 && pv && abase < p) {
                     T.C32[p * T.c32_stride + (pbase + pi)] = w;
                     if (w) T.rowflag[p] = 1;
                 }
