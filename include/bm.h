@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define BM_ABI_VERSION 1
+#define BM_ABI_VERSION 2
 
 typedef enum {
     BM_OK = 0,
@@ -127,6 +127,9 @@ typedef struct {
     double  ms_range_events;      /* summed HIP-event intervals around the same launches on the
                                      library's stream (profile = 1); each also holds the
                                      dispatch's wait behind the previous kernel               */
+    double  ms_resolve_kernel;    /* summed execution windows of the matrix-core candidate
+                                     resolves, first wave start to the last workgroup's exit
+                                     before the accept it runs (profile = 1, single builds)   */
 } bm_stats;
 
 typedef struct {
@@ -225,6 +228,22 @@ int bm_error_bound(int32_t path, int32_t dtype, int32_t d, double eps, double ma
  * run (BM_EINTERNAL) if a layout bit is missing.
  */
 int bm_device_selfcheck(int32_t device, int32_t *flags);
+
+/*
+ * Give back the memory the library keeps between calls.  Each call hands the
+ * device blocks, pinned staging buffers and streams it used to a process-wide
+ * cache once its stream has drained, and later calls on the same device reuse
+ * them instead of allocating again (hipMalloc, hipFree and hipHostMalloc cost
+ * tens to hundreds of microseconds each, and hipFree waits for the device).
+ * Device memory kept is at most BM_CACHE_BYTES bytes per device (environment,
+ * read once per device; default an eighth of the device's memory; 0 keeps
+ * none).  This frees the cached device blocks and pinned buffers of `device`
+ * (-1: every device); idle streams are kept.  Results are never cached: they
+ * belong to the caller until bm_result_free.  Safe to call at any time from
+ * any thread; calls in flight keep what they hold.  Returns BM_OK, or
+ * BM_EINVAL for a device that does not exist.
+ */
+int bm_trim_cache(int32_t device);
 
 /* Free a result from any entry point (host or device arrays).  NULL-safe. */
 void bm_result_free(bm_result *r);

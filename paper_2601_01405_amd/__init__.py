@@ -49,7 +49,7 @@ class Stats(ctypes.Structure):
                 ("band_pairs", ctypes.c_int64), ("blocks", ctypes.c_int64), ("candidates", ctypes.c_int64),
                 ("path", ctypes.c_int32), ("block", ctypes.c_int32), ("ms_range_kernel", ctypes.c_double),
                 ("range_launches", ctypes.c_int64), ("range_pairs", ctypes.c_int64),
-                ("ms_range_events", ctypes.c_double)]
+                ("ms_range_events", ctypes.c_double), ("ms_resolve_kernel", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -107,6 +107,8 @@ def load_library(path: str = LIB_PATH):
     lib.bm_error_bound.restype = ctypes.c_int
     lib.bm_device_selfcheck.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     lib.bm_device_selfcheck.restype = ctypes.c_int
+    lib.bm_trim_cache.argtypes = [ctypes.c_int32]
+    lib.bm_trim_cache.restype = ctypes.c_int
     for f in ("bm_default_options", "bm_build", "bm_range_sets", "bm_build_many"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -115,7 +117,7 @@ def load_library(path: str = LIB_PATH):
 
 EXPORTED_SYMBOLS = ("bm_default_options", "bm_build", "bm_build_many", "bm_range_sets", "bm_result_free",
                     "bm_last_error", "bm_device_count", "bm_abi_version", "bm_error_bound",
-                    "bm_device_selfcheck")
+                    "bm_device_selfcheck", "bm_trim_cache")
 
 
 class Bound(ctypes.Structure):
@@ -328,3 +330,9 @@ def build_many(problems, **kw):
 
 def device_count() -> int:
     return int(load_library().bm_device_count())
+
+
+def trim_cache(device: int = -1) -> None:
+    """Free the device blocks and pinned buffers the library keeps between
+    calls (bm_trim_cache); device -1 = every device."""
+    _check(load_library().bm_trim_cache(int(device)))

@@ -168,11 +168,13 @@ bm_result *run_job(const Job &job, const bm_options &o)
         } ev_guard{evs};
         SettledSet sd{};
         // device-clock execution windows of the range passes (profile = 1)
-        KernelClock *kclk = nullptr;
+        // ([0] range passes, [1] resolves)
+        KernelClock *kclk = nullptr, *rclk = nullptr;
         if (o.profile) {
-            kclk = dev.alloc<KernelClock>(1);
-            const KernelClock init{~0ull, 0ull, 0ull};
-            dev.upload(kclk, &init, sizeof init);
+            kclk = dev.alloc<KernelClock>(2);
+            const KernelClock init[2] = {{~0ull, 0ull, 0ull}, {~0ull, 0ull, 0ull}};
+            dev.upload(kclk, init, sizeof init);
+            rclk = kclk + 1;
         }
         auto range_task = [&](const int32_t *Alist, const int64_t *blk, uint64_t *covered) {
             RangeTask t{};
@@ -348,7 +350,9 @@ bm_result *run_job(const Job &job, const bm_options &o)
             // open before the loop.  FP32 path: open, exact resolve, accept, range.
             auto enqueue_block = [&](hipStream_t s, bool events) {
                 if (mfma) {
-                    hip_ok(launch_range_tasks(rtask + 1, nullptr, res_wgs, ma.kind, ma.S, true, s), "resolve_mfma");
+                    const LaunchEvents rev{nullptr, nullptr, events ? rclk : nullptr};
+                    hip_ok(launch_range_tasks(rtask + 1, nullptr, res_wgs, ma.kind, ma.S, true, s, rev),
+                           "resolve_mfma");
                     run_range_on(s, events, rtask, A, &st->L0, covered);
                     return;
                 }
@@ -437,10 +441,13 @@ bm_result *run_job(const Job &job, const bm_options &o)
             res->stats.ms_range_events += ms;
         }
         if (kclk) {
-            const KernelClock kc = dev.fetch(kclk);
+            const KernelClock kc = dev.fetch(kclk), rc = dev.fetch(rclk);
             int khz = 0;
             hip_ok(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev.dev), "wall clock rate");
-            if (khz > 0) res->stats.ms_range_kernel = (double)kc.ticks / (double)khz;
+            if (khz > 0) {
+                res->stats.ms_range_kernel = (double)kc.ticks / (double)khz;
+                res->stats.ms_resolve_kernel = (double)rc.ticks / (double)khz;
+            }
         }
         res->stats.band_pairs = (int64_t)hs.band;
         res->stats.pairs_useful = L * n;
@@ -632,6 +639,19 @@ int bm_build_many(const bm_problem *probs, int32_t n_probs, const bm_options *op
             outs[k] = nullptr;
         }
     return rc;
+}
+
+int bm_trim_cache(int32_t device)
+{
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess) count = 0;
+    if (device < -1 || device >= count) {
+        g_last_error = "bm_trim_cache: no such device";
+        return BM_EINVAL;
+    }
+    cache_trim(device);
+    g_last_error.clear();
+    return BM_OK;
 }
 
 void bm_result_free(bm_result *r)

@@ -53,8 +53,127 @@ inline size_t dtype_size(int32_t dtype) { return dtype == BM_F64 ? 8 : dtype == 
 
 inline int bitlen(uint64_t v) { return v ? 64 - __builtin_clzll(v) : 0; }
 
-// ---- device context: selected device, stream, tracked allocations ------------------------
+// ---- process-wide cache of device memory, pinned staging and streams --------------------
+// A build hands what it allocated back here once its stream has drained, and
+// later builds on the same device take it instead of calling hipMalloc, hipFree
+// (which waits for the whole device), hipHostMalloc and hipStreamCreate again.
+// Device memory kept per device is bounded by BM_CACHE_BYTES (bytes; default an
+// eighth of the device's memory, 0 keeps nothing); bm_trim_cache frees it.
 constexpr size_t kPinnedBytes = 64 * 1024;
+struct Cache {
+    struct Dev {
+        std::vector<std::pair<void *, size_t>> blocks;      // (pointer, size) of free device blocks
+        size_t bytes = 0, limit = 0;
+        bool limit_set = false;
+        std::vector<void *> pinned;                         // free kPinnedBytes host buffers
+        std::vector<hipStream_t> streams;                   // idle non-blocking streams
+    };
+    std::mutex mu;
+    std::map<int, Dev> devs;
+};
+inline Cache &cache()
+{
+    static Cache *c = new Cache;                            // never destroyed: usable until exit
+    return *c;
+}
+// Allocation sizes: powers of two up to 1 MiB, whole 2 MiB pages above.
+inline size_t size_class(size_t b)
+{
+    if (b <= ((size_t)1 << 20)) {
+        size_t c = 256;
+        while (c < b) c <<= 1;
+        return c;
+    }
+    const size_t page = (size_t)2 << 20;
+    return (b + page - 1) / page * page;
+}
+// Best fit among `blocks` for a request of class `cls`: at most 50% larger.
+inline int best_fit(const std::vector<std::pair<void *, size_t>> &blocks, size_t cls)
+{
+    int best = -1;
+    for (size_t i = 0; i < blocks.size(); ++i) {
+        const size_t z = blocks[i].second;
+        if (z >= cls && z <= cls + cls / 2 && (best < 0 || z < blocks[(size_t)best].second)) best = (int)i;
+    }
+    return best;
+}
+inline Cache::Dev &cache_dev(Cache &c, int dev)             // (c.mu held)
+{
+    Cache::Dev &d = c.devs[dev];
+    if (!d.limit_set) {
+        d.limit_set = true;
+        const char *env = std::getenv("BM_CACHE_BYTES");
+        if (env && *env) {
+            d.limit = (size_t)std::strtoull(env, nullptr, 10);
+        } else {
+            size_t total = 0;
+            if (hipDeviceTotalMem(&total, dev) != hipSuccess) total = 0;
+            d.limit = total / 8;
+        }
+    }
+    return d;
+}
+inline void *cache_take(int dev, size_t cls, size_t *got)
+{
+    Cache &c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    Cache::Dev &d = cache_dev(c, dev);
+    const int i = best_fit(d.blocks, cls);
+    if (i < 0) return nullptr;
+    void *p = d.blocks[(size_t)i].first;
+    *got = d.blocks[(size_t)i].second;
+    d.bytes -= *got;
+    d.blocks.erase(d.blocks.begin() + i);
+    return p;
+}
+// Keep a drained block (device `dev` current), or free it past the limit.
+inline void cache_give(int dev, void *p, size_t bytes)
+{
+    Cache &c = cache();
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        Cache::Dev &d = cache_dev(c, dev);
+        if (d.bytes + bytes <= d.limit) {
+            d.blocks.emplace_back(p, bytes);
+            d.bytes += bytes;
+            return;
+        }
+    }
+    (void)hipFree(p);
+}
+// Free the cached device blocks and pinned buffers of one device (-1: all);
+// the caller has the device current when dev >= 0.
+inline void cache_trim(int dev)
+{
+    Cache &c = cache();
+    std::vector<std::pair<void *, size_t>> blocks;
+    std::vector<void *> pinned;
+    std::vector<int> owners;
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        for (auto &kv : c.devs) {
+            if (dev >= 0 && kv.first != dev) continue;
+            for (auto &b : kv.second.blocks) {
+                blocks.push_back(b);
+                owners.push_back(kv.first);
+            }
+            kv.second.blocks.clear();
+            kv.second.bytes = 0;
+            pinned.insert(pinned.end(), kv.second.pinned.begin(), kv.second.pinned.end());
+            kv.second.pinned.clear();
+        }
+    }
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    for (size_t i = 0; i < blocks.size(); ++i) {
+        (void)hipSetDevice(owners[i]);
+        (void)hipFree(blocks[i].first);
+    }
+    if (cur >= 0) (void)hipSetDevice(cur);
+    for (void *p : pinned) (void)hipHostFree(p);
+}
+
+// ---- device context: selected device, stream, tracked allocations ------------------------
 constexpr size_t kUploadStage = kPinnedBytes - 4096;
 constexpr int kUploadBlocks = 64;                   // blocks per table of directly launched passes
 static_assert(kUploadBlocks * 32 <= 2048, "block table staging");
@@ -64,7 +183,8 @@ struct Device {
     hipStream_t s = nullptr;
     bool own_stream = false;
     int64_t budget = 0, used = 0;
-    std::vector<std::pair<void *, size_t>> bufs;
+    std::vector<std::pair<void *, size_t>> bufs;    // held by this build (size = allocated class)
+    std::vector<std::pair<void *, size_t>> spare;   // released during the build: reusable on its stream
     void *pinned = nullptr;
 
     explicit Device(const bm_options &o)
@@ -76,38 +196,109 @@ struct Device {
         if (dev >= count) fail(BM_ENODEVICE, "options.device is out of range");
         hip_ok(hipSetDevice(dev), "hipSetDevice");
         budget = o.max_device_bytes;
+        {
+            Cache &c = cache();
+            std::lock_guard<std::mutex> lk(c.mu);
+            Cache::Dev &d = cache_dev(c, dev);
+            if (!o.stream && !d.streams.empty()) {
+                s = d.streams.back();
+                d.streams.pop_back();
+                own_stream = true;
+            }
+            if (!d.pinned.empty()) {
+                pinned = d.pinned.back();
+                d.pinned.pop_back();
+            }
+        }
         if (o.stream) {
             s = (hipStream_t)o.stream;
-        } else {
+        } else if (!s) {
             hip_ok(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
             own_stream = true;
         }
-        hip_ok(hipHostMalloc(&pinned, kPinnedBytes, hipHostMallocDefault), "hipHostMalloc");
+        if (!pinned) hip_ok(hipHostMalloc(&pinned, kPinnedBytes, hipHostMallocDefault), "hipHostMalloc");
     }
     ~Device()
     {
-        if (s) (void)hipStreamSynchronize(s);
-        for (auto &b : bufs) (void)hipFree(b.first);
-        if (pinned) (void)hipHostFree(pinned);
-        if (own_stream && s) (void)hipStreamDestroy(s);
+        // once the stream has drained, what this build holds goes back to the
+        // cache; after a failed wait it is freed instead
+        const bool drained = !s || hipStreamSynchronize(s) == hipSuccess;
+        for (auto *list : {&bufs, &spare})
+            for (auto &b : *list) {
+                if (drained) cache_give(dev, b.first, b.second);
+                else (void)hipFree(b.first);
+            }
+        bool kept_pinned = false, kept_stream = false;
+        if (drained) {
+            Cache &c = cache();
+            std::lock_guard<std::mutex> lk(c.mu);
+            Cache::Dev &d = cache_dev(c, dev);
+            if (pinned) {
+                d.pinned.push_back(pinned);
+                kept_pinned = true;
+            }
+            if (own_stream && s) {
+                d.streams.push_back(s);
+                kept_stream = true;
+            }
+        }
+        if (pinned && !kept_pinned) (void)hipHostFree(pinned);
+        if (own_stream && s && !kept_stream) (void)hipStreamDestroy(s);
         if (prev_dev >= 0) (void)hipSetDevice(prev_dev);
     }
     Device(const Device &) = delete;
     Device &operator=(const Device &) = delete;
 
+    // Free the spare blocks (waiting for the stream first).
+    void drop_spare()
+    {
+        if (spare.empty()) return;
+        sync();
+        for (auto &b : spare) {
+            (void)hipFree(b.first);
+            used -= (int64_t)b.second;
+        }
+        spare.clear();
+    }
+    // A device block of at least `bytes`: from this build's spare blocks, the
+    // cache, or hipMalloc (after freeing the cached blocks when that fails).
     void *raw_alloc(size_t bytes, bool tracked)
     {
         if (bytes == 0) bytes = 16;
-        if (budget > 0 && used + (int64_t)bytes > budget)
-            fail(BM_ENOMEM, "device memory cap (options.max_device_bytes) exceeded");
+        const size_t cls = size_class(bytes);
         void *p = nullptr;
-        hipError_t e = hipMalloc(&p, bytes);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            fail(BM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        size_t got = 0;
+        const int i = best_fit(spare, cls);
+        if (i >= 0) {
+            p = spare[(size_t)i].first;
+            got = spare[(size_t)i].second;
+            spare.erase(spare.begin() + i);
+        } else {
+            if (budget > 0 && used + (int64_t)cls > budget) drop_spare();
+            if (budget > 0 && used + (int64_t)cls > budget)
+                fail(BM_ENOMEM, "device memory cap (options.max_device_bytes) exceeded");
+            p = cache_take(dev, cls, &got);
+            if (p && budget > 0 && used + (int64_t)got > budget) {     // larger than the cap allows
+                cache_give(dev, p, got);
+                p = nullptr;
+            }
+            if (!p) {
+                got = cls;
+                hipError_t e = hipMalloc(&p, cls);
+                if (e != hipSuccess) {
+                    (void)hipGetLastError();
+                    cache_trim(dev);
+                    drop_spare();
+                    e = hipMalloc(&p, cls);
+                }
+                if (e != hipSuccess) {
+                    (void)hipGetLastError();
+                    fail(BM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+                }
+            }
+            used += (int64_t)got;
         }
-        used += (int64_t)bytes;
-        if (tracked) bufs.emplace_back(p, bytes);
+        if (tracked) bufs.emplace_back(p, got);
         return p;
     }
     template <class T> T *alloc(size_t count) { return (T *)raw_alloc(count * sizeof(T), true); }
@@ -117,12 +308,13 @@ struct Device {
         hip_ok(hipMemsetAsync(p, 0, std::max<size_t>(count * sizeof(T), 1), s), "hipMemsetAsync");
         return p;
     }
+    // The block is no longer needed: later allocations of this build may reuse
+    // it (they are ordered after its last use on the same stream).
     void release(void *p)
     {
         for (size_t i = 0; i < bufs.size(); ++i)
             if (bufs[i].first == p) {
-                (void)hipFree(p);
-                used -= (int64_t)bufs[i].second;
+                spare.push_back(bufs[i]);
                 bufs.erase(bufs.begin() + (long)i);
                 return;
             }

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_function():
     for name in names:
         assert hasattr(lib, name), f"{name} declared in bm.h but not exported"
     assert set(names) == set(bm.EXPORTED_SYMBOLS)
-    assert lib.bm_abi_version() == 1
+    assert lib.bm_abi_version() == 2
 
 
 def test_struct_layouts_match_header(tmp_path):
@@ -104,3 +104,10 @@ def test_no_device_reported():
 
 def test_result_free_is_null_safe():
     bm.load_library().bm_result_free(None)
+
+
+def test_trim_cache_rejects_unknown_device():
+    lib = bm.load_library()
+    assert lib.bm_trim_cache(-2) == bm.BM_EINVAL
+    assert lib.bm_trim_cache(1 << 20) == bm.BM_EINVAL
+    assert b"no such device" in lib.bm_last_error()
