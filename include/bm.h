@@ -130,6 +130,10 @@ typedef struct {
     double  ms_resolve_kernel;    /* summed execution windows of the matrix-core candidate
                                      resolves, first wave start to the last workgroup's exit
                                      before the accept it runs (profile = 1, single builds)   */
+    double  ms_serial_steps;      /* summed device time of the serial steps between passes (the
+                                     accept after each resolve, the opening of the next block
+                                     after each range pass), each run by the last workgroup of
+                                     its pass (profile = 1, single builds, matrix-core paths) */
 } bm_stats;
 
 typedef struct {

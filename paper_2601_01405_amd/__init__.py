@@ -49,7 +49,8 @@ class Stats(ctypes.Structure):
                 ("band_pairs", ctypes.c_int64), ("blocks", ctypes.c_int64), ("candidates", ctypes.c_int64),
                 ("path", ctypes.c_int32), ("block", ctypes.c_int32), ("ms_range_kernel", ctypes.c_double),
                 ("range_launches", ctypes.c_int64), ("range_pairs", ctypes.c_int64),
-                ("ms_range_events", ctypes.c_double), ("ms_resolve_kernel", ctypes.c_double)]
+                ("ms_range_events", ctypes.c_double), ("ms_resolve_kernel", ctypes.c_double),
+                ("ms_serial_steps", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}

@@ -172,7 +172,7 @@ bm_result *run_job(const Job &job, const bm_options &o)
         KernelClock *kclk = nullptr, *rclk = nullptr;
         if (o.profile) {
             kclk = dev.alloc<KernelClock>(2);
-            const KernelClock init[2] = {{~0ull, 0ull, 0ull}, {~0ull, 0ull, 0ull}};
+            const KernelClock init[2] = {{~0ull, 0ull, 0ull, 0ull}, {~0ull, 0ull, 0ull, 0ull}};
             dev.upload(kclk, init, sizeof init);
             rclk = kclk + 1;
         }
@@ -447,6 +447,7 @@ bm_result *run_job(const Job &job, const bm_options &o)
             if (khz > 0) {
                 res->stats.ms_range_kernel = (double)kc.ticks / (double)khz;
                 res->stats.ms_resolve_kernel = (double)rc.ticks / (double)khz;
+                res->stats.ms_serial_steps = (double)(kc.tail + rc.tail) / (double)khz;
             }
         }
         res->stats.band_pairs = (int64_t)hs.band;

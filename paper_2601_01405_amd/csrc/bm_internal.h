@@ -87,9 +87,10 @@ inline size_t mfma_operand_words(int64_t points, int S)
 
 // Execution window of a kernel on the device clock: every workgroup lowers
 // `start` at entry; the last one to finish adds (now - start) to `ticks` and
-// resets `start` and `done` for the next launch.
+// resets `start` and `done` for the next launch.  `tail` sums the time of the
+// serial step a task's last workgroup runs after the window (accept or open).
 struct KernelClock {
-    unsigned long long start, done, ticks;
+    unsigned long long start, done, ticks, tail;
 };
 
 enum { T3_U = 0, T3_V = 1, T3_Z = 2 };

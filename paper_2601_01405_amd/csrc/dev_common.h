@@ -9,18 +9,36 @@ namespace bm {
 
 typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
 
+// ---- global-memory access ------------------------------------------------------------
+// A pointer read from a task table (rather than passed as a kernel argument)
+// reaches the compiler as a generic pointer, accessed with FLAT instructions.
+// Those count in the same wait counter as LDS operations, so every wait for an
+// LDS read or a lane shuffle would also wait for all global loads in flight
+// (the prefetched stages of a pass).  Every array this library hands to a
+// kernel is global memory; gbl() says so, and the accesses become global ones.
+#define BM_GLOBAL __attribute__((address_space(1)))
+template <class T> __device__ __forceinline__ BM_GLOBAL T *gbl(T *p) { return (BM_GLOBAL T *)p; }
+template <class T> __device__ __forceinline__ T gatomic_add(T *p, T v)
+{
+    return __hip_atomic_fetch_add(gbl(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T> __device__ __forceinline__ T gatomic_or(T *p, T v)
+{
+    return __hip_atomic_fetch_or(gbl(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ---- exact widening of a stored coordinate -------------------------------------------
 template <int DT>
 __device__ __forceinline__ double load_coord(const void *X, int64_t off)
 {
-    if constexpr (DT == 0) return ((const double *)X)[off];
-    else if constexpr (DT == 1) return (double)((const float *)X)[off];
-    else return (double)(float)((const _Float16 *)X)[off];   // binary16 -> f32 -> f64, exact
+    if constexpr (DT == 0) return ((const BM_GLOBAL double *)X)[off];
+    else if constexpr (DT == 1) return (double)((const BM_GLOBAL float *)X)[off];
+    else return (double)(float)((const BM_GLOBAL _Float16 *)X)[off];   // binary16 -> f32 -> f64, exact
 }
 
 __device__ __forceinline__ int64_t orig_index(const PointsView &P, int64_t rank)
 {
-    return P.perm ? (int64_t)P.perm[rank] : rank;
+    return P.perm ? (int64_t)gbl(P.perm)[rank] : rank;
 }
 
 // ---- the FP64 predicate --------------------------------------------------------------

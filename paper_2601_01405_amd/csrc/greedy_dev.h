@@ -19,16 +19,57 @@ namespace bm {
 constexpr int MAX_B = 8192;
 
 // LDS bytes the steps use (from a caller-provided, 16-byte aligned buffer).
-template <int NT> constexpr size_t open_lds_bytes() { return 16 + (size_t)NT / 64 * 4 + (size_t)NT * 16; }
+template <int NT> constexpr size_t open_lds_bytes()
+{
+    return 16 + (size_t)NT / 64 * 4 + (size_t)NT * 16 + (size_t)MAX_B * 4;
+}
 template <int NT> constexpr size_t accept_lds_bytes()
 {
-    return (size_t)MAX_B / 64 * 16 + 16 + (size_t)NT / 64 * 4 + (size_t)MAX_B * 2;
+    return (size_t)MAX_B / 64 * 16 + 16 + ((size_t)MAX_B / 64 + 4) * 4 + (size_t)MAX_B * 2;
+}
+
+// Exclusive prefix of per-wave counts in (k, wave) order, for a workgroup whose
+// thread t holds items k * NT + t (k < MAX_B / NT): cnt[k] is this wave's count
+// of item row k (wave-uniform).  tab gets MAX_B / 64 + 1 ints: the bases, then
+// the total, which is returned; tab[k * NT / 64 + wave] is the wave's base.
+template <int NT, int RUN>
+__device__ int slot_scan(const int (&cnt)[RUN], int *tab)
+{
+    constexpr int NW = NT / 64, E = RUN * NW, PER = (E + 63) / 64;
+    static_assert(E == MAX_B / 64, "one entry per bitmap word");
+    const int lane = lane_id(), wid = (int)(threadIdx.x >> 6);
+    __syncthreads();                                             // tab's previous use is over
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < RUN; ++k) tab[k * NW + wid] = cnt[k];
+    }
+    __syncthreads();
+    if (wid == 0) {
+        int v[PER], sum = 0;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = lane * PER + i;
+            v[i] = e < E ? tab[e] : 0;
+            sum += v[i];
+        }
+        const int incl = wave_incl_scan(sum);
+        int run = incl - sum;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = lane * PER + i;
+            if (e < E) tab[e] = run;
+            run += v[i];
+        }
+        if (lane == 63) tab[E] = incl;
+    }
+    __syncthreads();
+    return tab[E];
 }
 
 // Open a block of chain T:
 //  1. Gather: scan the covered bitmap from the cursor, 64 ranks per thread per
-//     sweep, and list up to B uncovered ranks in increasing order; clear
-//     rowflag[0..B).
+//     sweep, and list up to B uncovered ranks in increasing order (in LDS,
+//     then copied out coalesced); clear rowflag[0..B).
 //  2. (settle) Every rank below the first candidate is final (a landmark, or
 //     covered and never a landmark).  The non-landmarks among ranks [rlo, R),
 //     R = that candidate rounded down to a tile, are appended in rank order to
@@ -43,8 +84,9 @@ __device__ void block_open(const ChainTask &T, unsigned char *lds)
     int32_t *sh_first = (int32_t *)(lds + 8);
     int *sh_scan = (int *)(lds + 16);
     int32_t *sel = (int32_t *)(lds + 16 + NT / 64 * 4);
+    int32_t *clist = sel + NT * 4;                               // [MAX_B] the gathered ranks
     const int tid = (int)threadIdx.x;
-    GreedyState *st = T.st;
+    BM_GLOBAL GreedyState *st = gbl(T.st);
     const int64_t n = T.n;
     const int B = T.B;
     if (st->done) {                                              // workgroup-uniform
@@ -54,7 +96,7 @@ __device__ void block_open(const ChainTask &T, unsigned char *lds)
         }
         return;
     }
-    for (int j = tid; j < B; j += NT) T.rowflag[j] = 0;
+    for (int j = tid; j < B; j += NT) gbl(T.rowflag)[j] = 0;
     const int64_t nwords = (n + 63) >> 6;
     int64_t cur = st->cursor;
     const int64_t R0 = st->rlo;
@@ -70,7 +112,7 @@ __device__ void block_open(const ChainTask &T, unsigned char *lds)
         const int64_t w = w0 + tid;
         uint64_t msk = 0;
         if (w < nwords) {
-            msk = ~T.covered[w];
+            msk = ~gbl(T.covered)[w];
             if (w == w0) msk &= (~0ull) << (cur & 63);
             if (w == nwords - 1 && (n & 63)) msk &= (1ull << (n & 63)) - 1;
         }
@@ -78,10 +120,10 @@ __device__ void block_open(const ChainTask &T, unsigned char *lds)
         const int pre = block_excl_scan<NT>((int)__popcll(msk), &total, sh_scan);
         const int room = B - count;
         int k = pre;
-        while (msk && k < room) {
+        while (msk && k < room) {                                // into LDS: a thread's ranks are adjacent
             const int b = __ffsll((unsigned long long)msk) - 1;
             const int64_t r = (w << 6) + b;
-            T.cand[count + k] = (int32_t)r;
+            clist[count + k] = (int32_t)r;
             if (count + k == 0) *sh_first = (int32_t)r;
             if (count + k == B - 1) *sh_cursor = r + 1;
             msk &= msk - 1;
@@ -94,7 +136,8 @@ __device__ void block_open(const ChainTask &T, unsigned char *lds)
             cur = (w0 + NT) << 6;
         }
     }
-    __syncthreads();                                             // cand[], sh_first visible to the workgroup
+    __syncthreads();                                             // clist, sh_first visible to the workgroup
+    for (int j = tid; j < count; j += NT) gbl(T.cand)[j] = clist[j];  // coalesced
 
     int64_t R1 = R0;
     if (T.settle && count > 0) {
@@ -110,7 +153,7 @@ __device__ void block_open(const ChainTask &T, unsigned char *lds)
             const int64_t w = w0 + tid;
             uint64_t msk = 0;
             if ((w << 6) < R1) {
-                msk = ~T.islm[w];
+                msk = ~gbl(T.islm)[w];
                 const int64_t lo = w << 6;
                 if (lo < R0) msk &= (~0ull) << (R0 - lo);        // R0 - lo is 0 or 32
                 if (R1 - lo < 64) msk &= (1ull << (R1 - lo)) - 1;
@@ -124,8 +167,8 @@ __device__ void block_open(const ChainTask &T, unsigned char *lds)
                 const int64_t r = (w << 6) + b;
                 const int64_t j = m + k;
 #pragma unroll
-                for (int q = 0; q < 3; ++q) sd.T3[t3_index(j, q)] = a.T3[t3_index(r, q)];
-                sd.idx[j] = T.perm ? T.perm[r] : (int32_t)r;
+                for (int q = 0; q < 3; ++q) gbl(sd.T3)[t3_index(j, q)] = gbl(a.T3)[t3_index(r, q)];
+                gbl(sd.idx)[j] = T.perm ? gbl(T.perm)[r] : (int32_t)r;
                 if (k < kSel) sel[k] = (int32_t)r;
             }
             __syncthreads();
@@ -135,7 +178,7 @@ __device__ void block_open(const ChainTask &T, unsigned char *lds)
                     int k = pre;
                     uint64_t mm = 0;
                     if ((w << 6) < R1) {
-                        mm = ~T.islm[w];
+                        mm = ~gbl(T.islm)[w];
                         const int64_t lo = w << 6;
                         if (lo < R0) mm &= (~0ull) << (R0 - lo);
                         if (R1 - lo < 64) mm &= (1ull << (R1 - lo)) - 1;
@@ -153,7 +196,7 @@ __device__ void block_open(const ChainTask &T, unsigned char *lds)
                     const int64_t src = sel[q], dst = m + q0 + q;
                     const int64_t so = ((((src >> 5) * S + ss) * 64) + (src & 31) + 32 * half) * 8;
                     const int64_t dof = ((((dst >> 5) * S + ss) * 64) + (dst & 31) + 32 * half) * 8;
-                    *(u32x4 *)(sd.Pop + dof) = *(const u32x4 *)(a.Pop + so);
+                    *(BM_GLOBAL u32x4 *)gbl(sd.Pop + dof) = *(const BM_GLOBAL u32x4 *)gbl(a.Pop + so);
                 }
             }
             m += total;
@@ -167,7 +210,7 @@ __device__ void block_open(const ChainTask &T, unsigned char *lds)
         st->cursor = (count == B) ? *sh_cursor : n;
         if (count == 0) {
             st->done = 1;
-            if (T.ndone) atomicAdd(T.ndone, 1ull);
+            if (T.ndone) gatomic_add(T.ndone, 1ull);
         } else {
             st->blocks += 1;
             st->candidates += (unsigned long long)count;
@@ -186,21 +229,24 @@ __device__ void block_open(const ChainTask &T, unsigned char *lds)
 // accepted once all of them are rejected.  Decisions never change, so a stale
 // view only delays one; the earliest undecided candidate always has all its
 // conflicts decided, so every round decides at least one.  The result equals
-// the sequential scan.  Each thread takes a contiguous run of candidates for
-// the listing and the compaction (one block scan each); in a round one wave
-// takes one flagged row, lane w reading conflict words w, w + 64 (coalesced).  The accepted ranks go to A (the range pass's list), the
-// landmark list (original indices) and lm_rank at ordinal st->L, and the
-// block is recorded in blog[(st->blocks - 1) % kBlockLogSize].
+// the sequential scan.  Thread t holds candidates k * NT + t, so each wave's
+// lanes cover one bitmap word per k and every load and store coalesces; the
+// listing and the compaction take one slot scan each.  In a round one wave
+// takes one flagged row, lane w reading conflict words w, w + 64 (coalesced).
+// The accepted ranks go to A (the range pass's list), the landmark list
+// (original indices) and lm_rank at ordinal st->L, and the block is recorded
+// in blog[(st->blocks - 1) % kBlockLogSize].
 template <int NT>
 __device__ void block_accept(const ChainTask &T, unsigned char *lds)
 {
     constexpr int NWAVES = NT / 64;
-    unsigned long long *acc = (unsigned long long *)lds;
-    unsigned long long *rej = acc + MAX_B / 64;
+    constexpr int RUN = MAX_B / NT;
+    unsigned long long *acc = (unsigned long long *)lds;        // [MAX_B / 64] accepted
+    unsigned long long *rej = acc + MAX_B / 64;                 // [MAX_B / 64] rejected
     int *sh_undecided = (int *)(rej + MAX_B / 64);
-    int *sh_scan = sh_undecided + 4;
-    int16_t *flist = (int16_t *)(sh_scan + NT / 64);
-    GreedyState *st = T.st;
+    int *tab = sh_undecided + 4;                                // [MAX_B / 64 + 4] slot bases
+    int16_t *flist = (int16_t *)(tab + MAX_B / 64 + 4);         // [MAX_B] flagged rows
+    BM_GLOBAL GreedyState *st = gbl(T.st);
     const int nc = st->nc;
     const int tid = (int)threadIdx.x;
     if (nc == 0) {                                               // no block (the chain is done)
@@ -208,49 +254,49 @@ __device__ void block_accept(const ChainTask &T, unsigned char *lds)
         return;
     }
     const int64_t L0 = st->L;
-    const uint64_t *C = T.C;
+    const BM_GLOBAL uint64_t *C = gbl(T.C);
     const int nw = (T.B + 63) / 64;
     const int lane = lane_id(), wid = tid >> 6;
-    uint64_t *islm = T.settle ? T.islm : nullptr;
-    for (int t = tid; t < MAX_B / 64; t += NT) acc[t] = rej[t] = 0ull;
-    __syncthreads();
-    // rows with no earlier conflict are accepted; the flagged ones are listed in
-    // rank order.  Thread t takes the contiguous run [t * per, (t + 1) * per),
-    // its row flags and ranks loaded up front (independent loads).
-    constexpr int RUN = MAX_B / NT;
-    const int per = (nc + NT - 1) / NT;                          // <= RUN
-    const int j0 = tid * per, j1 = min(nc, j0 + per);
+    // Candidate j = k * NT + tid: the 64 lanes of a wave hold 64 consecutive
+    // candidates, one bitmap word, so loads and stores coalesce and a ballot
+    // is that word.  Rows with no earlier conflict are accepted at once.
     int32_t rank[RUN];
     uint32_t flagged = 0, inrun = 0;
+    // (unconditional loads, clamped into the block, so that all of them are
+    // in flight at once instead of one wait per branch)
+    int fl[RUN];
 #pragma unroll
     for (int k = 0; k < RUN; ++k) {
-        const int j = j0 + k;
-        const bool in = j < j1;
-        const int f = in ? T.rowflag[j] : 0;
-        rank[k] = in ? T.cand[j] : 0;
-        if (in) inrun |= 1u << k;
-        if (f) flagged |= 1u << k;
+        const int jc = min(k * NT + tid, nc - 1);
+        fl[k] = gbl(T.rowflag)[jc];
+        rank[k] = gbl(T.cand)[jc];
     }
-    {
-        // the run spans at most two bitmap words: one LDS atomic per word
-        uint32_t ok = inrun & ~flagged;
-        while (ok) {
-            const int k = __builtin_ctz(ok);
-            const int w = (j0 + k) >> 6;
-            unsigned long long bits = 0;
-            while (ok) {
-                const int kk = __builtin_ctz(ok);
-                if (((j0 + kk) >> 6) != w) break;
-                bits |= 1ull << ((j0 + kk) & 63);
-                ok &= ok - 1;
-            }
-            atomicOr(&acc[w], bits);
+#pragma unroll
+    for (int k = 0; k < RUN; ++k) {
+        if (k * NT + tid < nc) {
+            inrun |= 1u << k;
+            if (fl[k]) flagged |= 1u << k;
         }
     }
-    const int nfl = __popc(flagged);
-    int F;
-    int pre = block_excl_scan<NT>(nfl, &F, sh_scan);
-    for (uint32_t fl = flagged; fl; fl &= fl - 1) flist[pre++] = (int16_t)(j0 + __builtin_ctz(fl));
+    int cnt[RUN];
+#pragma unroll
+    for (int k = 0; k < RUN; ++k) {
+        const bool in = (inrun >> k) & 1u, f = (flagged >> k) & 1u;
+        const unsigned long long okb = __ballot(in && !f);
+        const unsigned long long fb = __ballot(f);
+        if (lane == 0) {
+            acc[k * NWAVES + wid] = okb;
+            rej[k * NWAVES + wid] = 0ull;
+        }
+        cnt[k] = (int)__popcll(fb);
+    }
+    // the flagged rows in rank order
+    const int F = slot_scan<NT, RUN>(cnt, tab);
+#pragma unroll
+    for (int k = 0; k < RUN; ++k) {
+        const unsigned long long fb = __ballot((flagged >> k) & 1u);
+        if ((flagged >> k) & 1u) flist[tab[k * NWAVES + wid] + mbcnt(fb)] = (int16_t)(k * NT + tid);
+    }
     __syncthreads();
     unsigned long long rounds = 0;
     while (F > 0) {                                              // uniform
@@ -293,38 +339,34 @@ __device__ void block_accept(const ChainTask &T, unsigned char *lds)
             break;
         }
     }
-    // the accepted candidates, compacted in rank order (each thread its run);
-    // landmark bits are merged per bitmap word before one atomic
+    // the accepted candidates, compacted in rank order
     uint32_t took = 0;
 #pragma unroll
-    for (int k = 0; k < RUN; ++k)
-        if (((inrun >> k) & 1u) && ((acc[(j0 + k) >> 6] >> ((j0 + k) & 63)) & 1ull)) took |= 1u << k;
+    for (int k = 0; k < RUN; ++k) {
+        const int j = k * NT + tid;
+        if (((inrun >> k) & 1u) && ((acc[j >> 6] >> (j & 63)) & 1ull)) took |= 1u << k;
+    }
     int32_t orig[RUN];
+    if (T.perm) {                                                // (unconditional loads: all in flight)
 #pragma unroll
-    for (int k = 0; k < RUN; ++k) orig[k] = ((took >> k) & 1u) && T.perm ? T.perm[rank[k]] : rank[k];
-    const int mine = __popc(took);
-    int total;
-    int pos = block_excl_scan<NT>(mine, &total, sh_scan);
-    int64_t word = -1;
-    unsigned long long bits = 0;
+        for (int k = 0; k < RUN; ++k) orig[k] = gbl(T.perm)[rank[k]];
+    } else {
+#pragma unroll
+        for (int k = 0; k < RUN; ++k) orig[k] = rank[k];
+    }
+#pragma unroll
+    for (int k = 0; k < RUN; ++k) cnt[k] = (int)__popcll(__ballot((took >> k) & 1u));
+    const int total = slot_scan<NT, RUN>(cnt, tab);
 #pragma unroll
     for (int k = 0; k < RUN; ++k) {
+        const unsigned long long tb = __ballot((took >> k) & 1u);
         if (!((took >> k) & 1u)) continue;
+        const int pos = tab[k * NWAVES + wid] + mbcnt(tb);
         const int32_t r = rank[k];
-        T.A[pos] = r;
-        T.landmarks[L0 + pos] = orig[k];
-        T.lm_rank[L0 + pos] = r;
-        ++pos;
-        if (islm) {
-            if ((r >> 6) != word) {
-                if (bits) atomicOr((unsigned long long *)&islm[word], bits);
-                word = r >> 6;
-                bits = 0;
-            }
-            bits |= 1ull << (r & 63);
-        }
+        gbl(T.A)[pos] = r;
+        gbl(T.landmarks)[L0 + pos] = orig[k];
+        gbl(T.lm_rank)[L0 + pos] = r;
     }
-    if (islm && bits) atomicOr((unsigned long long *)&islm[word], bits);
     if (tid == 0) {
         st->L0 = L0;
         st->na = total;
@@ -332,12 +374,12 @@ __device__ void block_accept(const ChainTask &T, unsigned char *lds)
         st->rounds += rounds;
         st->range_pairs += (unsigned long long)total * (unsigned long long)(st->m + T.n - st->rlo);
         st->accepted += 1;
-        BlockLog &b = T.blog[(st->blocks - 1) % kBlockLogSize];
+        BM_GLOBAL BlockLog &b = gbl(T.blog)[(st->blocks - 1) % kBlockLogSize];
         b.L0 = L0;
         b.na = total;
         b.rlo = st->rlo;
         b.m = st->m;
-        b.nkeys_before = *T.nkeys;
+        b.nkeys_before = *gbl(T.nkeys);
     }
 }
 

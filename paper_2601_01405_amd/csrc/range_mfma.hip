@@ -268,8 +268,13 @@ __device__ void range_wg_exit(const RangeTask &T, KernelClock *clk, unsigned cha
     }
     __syncthreads();                                               // (the acquire invalidated the CU's caches)
     if (!sh_last) return;
+    const unsigned long long t_in = clk ? (unsigned long long)wall_clock64() : 0ull;
     if (CONFLICT) block_accept<RM_THREADS>(*chain, smem);
     else block_open<RM_THREADS>(*chain, smem);
+    if (clk) {
+        __syncthreads();
+        if (threadIdx.x == 0) atomicAdd(&clk->tail, (unsigned long long)wall_clock64() - t_in);
+    }
 }
 
 // LDS of a range workgroup: the double-buffered stages, the accumulator
@@ -316,7 +321,7 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
     const MfmaArgs a = T.a;
     const PointsView P = T.P;
     const double e2 = T.e2;
-    const int32_t *__restrict__ A = T.A;
+    const BM_GLOBAL int32_t *A = gbl(T.A);
     const RangeOut o = T.o;
     const SettledSet sd = T.sd;
     const int NGW = T.NGW, chunks = T.chunks;
@@ -328,8 +333,8 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
     float *sC = (float *)(sT + 2 * THV);                           // [RM_THREADS] accumulator starts
     float *sN = sC + RM_THREADS;                                   // [RM_THREADS] norm bounds
 
-    const int64_t n = T.n_dev ? (int64_t)*T.n_dev : P.n;
-    const int64_t *blk = T.blk;
+    const int64_t n = T.n_dev ? (int64_t)*gbl(T.n_dev) : P.n;
+    const BM_GLOBAL int64_t *blk = gbl(T.blk);
     const int64_t ord0 = CONFLICT ? 0 : blk[0];
     const int na = CONFLICT ? (int)n : (int)blk[1];
     const int64_t msz = CONFLICT ? 0 : blk[3];                     // settled entries
@@ -342,6 +347,15 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
     const int kk = lb >> 3;
     const int g = kk % NGW;
     const int c = (kk / NGW) * 8 + xcd;
+    // the landmark bits of this pass's landmarks (one workgroup per landmark
+    // group sets them; the next block's settle step reads them after the pass)
+    if (!CONFLICT && c == 0 && T.chain && T.chain->settle) {
+        const int aj = g * RM_THREADS + tid;
+        if (aj < na) {
+            const int32_t r = A ? A[aj] : aj;
+            gatomic_or((unsigned long long *)&T.chain->islm[r >> 6], 1ull << (r & 63));
+        }
+    }
     if (g * RM_WAVES * RM_MP * 32 >= na) {                         // workgroup-uniform
         range_wg_exit<CONFLICT>(T, clk, smem);
         return;
@@ -367,8 +381,8 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
         float cv = 0.f, nv = 0.f;
         if (aj < na) {
             const int32_t r = A ? A[aj] : aj;
-            cv = a.cinit[r];
-            nv = a.nuup[r];
+            cv = gbl(a.cinit)[r];
+            nv = gbl(a.nuup)[r];
         }
         sC[tid] = cv;
         sN[tid] = nv;
@@ -419,7 +433,7 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
                 u32x4 v = {0u, 0u, 0u, 0u};
                 if (arank[pi] >= 0 && ss < S) {
                     const int64_t r = arank[pi];
-                    v = *(const u32x4 *)(a.Qop + ((((r >> 5) * S + ss) * 64) + (r & 31) + 32 * half) * 8);
+                    v = *(const BM_GLOBAL u32x4 *)gbl(a.Qop + ((((r >> 5) * S + ss) * 64) + (r & 31) + 32 * half) * 8);
                 }
                 areg[pi][s] = v;
             }
@@ -455,12 +469,12 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
             if (CONFLICT) {
                 const int sl = rem >> 6, ln = rem & 63;                 // step and lane of the vector
                 const int64_t r = A[min((int64_t)t * 32 + (ln & 31), n - 1)];
-                pre[k] = *(const u32x4 *)(a.Pop + ((((r >> 5) * S + sl) * 64) + (r & 31) + 32 * (ln >> 5)) * 8);
+                pre[k] = *(const BM_GLOBAL u32x4 *)gbl(a.Pop + ((((r >> 5) * S + sl) * 64) + (r & 31) + 32 * (ln >> 5)) * 8);
             } else {
                 const bool stl = t < MT;
                 const int64_t tl = stl ? t : t - MT + RT0;
                 const uint16_t *base = stl ? sd.Pop : a.Pop;
-                pre[k] = *(const u32x4 *)(base + (tl * tile_vecs + rem) * 8);
+                pre[k] = *(const BM_GLOBAL u32x4 *)gbl(base + (tl * tile_vecs + rem) * 8);
             }
         }
         {
@@ -472,14 +486,14 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
                 float v[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    v[e] = a.T3[t3_index(A[min((int64_t)t * 32 + p0 + e, n - 1)], which)];
+                    v[e] = gbl(a.T3)[t3_index(A[min((int64_t)t * 32 + p0 + e, n - 1)], which)];
                 pre_t = u32x4{__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
                               __float_as_uint(v[3])};
             } else {
                 const bool stl = t < MT;
                 const int64_t tl = stl ? t : t - MT + RT0;
                 const float *base = stl ? sd.T3 : a.T3;
-                pre_t = *(const u32x4 *)(base + tl * 96 + q * 4);
+                pre_t = *(const BM_GLOBAL u32x4 *)gbl(base + tl * 96 + q * 4);
             }
         }
     };
@@ -511,7 +525,7 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
             bool memb = false;
             int64_t xo = 0;
             if (have) {
-                xo = stl ? (int64_t)sd.idx[p] : orig_index(P, p);
+                xo = stl ? (int64_t)gbl(sd.idx)[p] : orig_index(P, p);
                 const int32_t lr = A ? A[ai] : ai;
                 // a landmark against its own point: s = 0 < e2
                 memb = (!stl && lr == p) || exact_member(P, orig_index(P, lr), xo, e2);
@@ -519,11 +533,11 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
             const uint64_t bal = __ballot(memb);
             if (!bal) continue;
             unsigned long long kb = 0;
-            if (lane == 0) kb = atomicAdd(o.nkeys, (unsigned long long)__popcll(bal));
+            if (lane == 0) kb = gatomic_add(o.nkeys, (unsigned long long)__popcll(bal));
             kb = __shfl(kb, 0, 64) + (unsigned long long)mbcnt(bal);
             if (memb) {
-                if (kb < o.cap) o.keys[kb] = ((uint64_t)(ord0 + ai) << o.bn) | (uint64_t)xo | o.tag;
-                if (!stl && o.covered) atomicOr((unsigned long long *)&o.covered[p >> 6], 1ull << (p & 63));
+                if (kb < o.cap) gbl(o.keys)[kb] = ((uint64_t)(ord0 + ai) << o.bn) | (uint64_t)xo | o.tag;
+                if (!stl && o.covered) gatomic_or((unsigned long long *)&o.covered[p >> 6], 1ull << (p & 63));
             }
         }
         qn = 0;
@@ -535,11 +549,11 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
         __syncthreads();
         const int kn = min(*kst_n, kKeyStage);
         if (kn == 0) return;                                        // workgroup-uniform
-        if (tid == 0) sh_kbase = atomicAdd(o.nkeys, (unsigned long long)kn);
+        if (tid == 0) sh_kbase = gatomic_add(o.nkeys, (unsigned long long)kn);
         __syncthreads();
         const unsigned long long kb = sh_kbase;
         for (int i = tid; i < kn; i += RM_THREADS)
-            if (kb + i < o.cap) o.keys[kb + i] = kst[i];
+            if (kb + i < o.cap) gbl(o.keys)[kb + i] = kst[i];
         __syncthreads();                                            // every copy has read the stage
         if (tid == 0) *kst_n = 0;
         __syncthreads();
@@ -623,7 +637,7 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
                         // candidate past the panel's first row (the words a row
                         // reads; the others are masked or never read)
                         const int64_t p = (int64_t)t * 32 + col;
-                        if (half == 0 && p < n && abase < p) T.C32[p * T.c32_stride + (pbase + pi)] = 0u;
+                        if (half == 0 && p < n && abase < p) gbl(T.C32)[p * T.c32_stride + (pbase + pi)] = 0u;
                     }
                     continue;
                 }
@@ -636,7 +650,7 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
             uint32_t mem = 0;
             // the point's original index: for the keys (range pass), or only when a
             // band pair needs the FP64 recheck (resolve)
-            const int64_t xo = (!pv || CONFLICT) ? 0 : stl ? (int64_t)sd.idx[p] : orig_index(P, p);
+            const int64_t xo = (!pv || CONFLICT) ? 0 : stl ? (int64_t)gbl(sd.idx)[p] : orig_index(P, p);
             if (a.refine) {
                 const float u = thr[col] - aw[pi];
                 const float v = thr[32 + col] + aw[pi];
@@ -693,8 +707,8 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
                     if ((mem >> i) & 1u) w |= 1u << acc_row(i, half);
                 w |= __shfl_xor(w, 32, 64);
                 if (half == 0 && pv && abase < p) {
-                    T.C32[p * T.c32_stride + (pbase + pi)] = w;
-                    if (w) T.rowflag[p] = 1;
+                    gbl(T.C32)[p * T.c32_stride + (pbase + pi)] = w;
+                    if (w) gbl(T.rowflag)[p] = 1;
                 }
                 continue;
             }
@@ -710,7 +724,7 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
             const int spill0 = max(lbase, kKeyStage);                  // first slot past the stage
             const int nspill = lbase + total - spill0;
             unsigned long long gbase = 0;
-            if (nspill > 0 && lane == 0) gbase = atomicAdd(o.nkeys, (unsigned long long)nspill);
+            if (nspill > 0 && lane == 0) gbase = gatomic_add(o.nkeys, (unsigned long long)nspill);
             gbase = __shfl(gbase, 0, 64);
             cov |= cnt != 0;
             int pos = lbase + incl - cnt;
@@ -719,7 +733,7 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
                 mem &= mem - 1;
                 const uint64_t key = ((uint64_t)(ord0 + abase + acc_row(i, half)) << o.bn) | (uint64_t)xo | o.tag;
                 if (pos < kKeyStage) kst[pos] = key;
-                else if (gbase + (pos - spill0) < o.cap) o.keys[gbase + (pos - spill0)] = key;
+                else if (gbase + (pos - spill0) < o.cap) gbl(o.keys)[gbase + (pos - spill0)] = key;
                 ++pos;
             }
         }
@@ -728,7 +742,7 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
             const uint64_t m = __ballot(cov);
             const uint64_t bits = (m | (m >> 32)) & 0xffffffffull;
             if (bits && lane == 0)
-                atomicOr((unsigned long long *)&o.covered[(tr * 32) >> 6], (unsigned long long)(bits << ((tr * 32) & 63)));
+                gatomic_or((unsigned long long *)&o.covered[(tr * 32) >> 6], (unsigned long long)(bits << ((tr * 32) & 63)));
         }
       }
     };
@@ -747,7 +761,7 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
     if (!CONFLICT && live) flush_queue();
     if (!CONFLICT) flush_keys();
     band = wave_sum(band);
-    if (band && lane == 0 && o.st) atomicAdd(&o.st->band, band);
+    if (band && lane == 0 && o.st) gatomic_add(&o.st->band, band);
     range_wg_exit<CONFLICT>(T, clk, smem);
 }
 
