@@ -87,7 +87,7 @@ typedef enum {           /* arithmetic of the range pass filter                 
 typedef struct {
     int32_t path;                 /* bm_path                                                   */
     int32_t refine;               /* 1 = exact (FP64 recheck of the band), 0 = unrefined       */
-    int32_t block;                /* candidate block size B: 0 = automatic, else 1..8192        */
+    int32_t block;                /* candidate block size B: 0 = automatic, else 1..16384       */
     int32_t device;               /* HIP device ordinal; -1 = the calling thread's current one */
     int32_t points_on_device;     /* 1: `points` is a device pointer on options.device          */
     int32_t results_on_device;    /* 1: result arrays stay in device memory                    */

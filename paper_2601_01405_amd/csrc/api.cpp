@@ -323,7 +323,7 @@ bm_result *run_job(const Job &job, const bm_options &o)
             // [0]: the greedy's range pass, whose last workgroup opens the next block;
             // [1]: the candidate resolve, whose last workgroup accepts.
             int32_t rNGW = 1, rchunks = 8;
-            if (mfma) range_grid(B, B, range_target_wg(), &rNGW, &rchunks);
+            if (mfma) range_grid(B, B, resolve_target_wg(), &rNGW, &rchunks);
             auto upload_tasks = [&]() {
                 RangeTask t[2];
                 t[0] = range_task(A, &st->L0, covered);

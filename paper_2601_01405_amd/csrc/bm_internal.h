@@ -8,6 +8,9 @@ namespace bm {
 // Stored point cloud on the device.  All per-point device arrays of the
 // driver are indexed by RANK (position in the visiting order); `perm` maps a
 // rank to the original row of `X` (nullptr = identity).
+// Largest candidate block B (the serial steps hold a block's bitmaps in LDS).
+constexpr int kMaxBlock = 16384;
+
 struct PointsView {
     const void *X;
     int64_t n;

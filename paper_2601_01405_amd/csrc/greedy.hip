@@ -11,14 +11,14 @@ constexpr int STEP_THREADS = 1024;
 
 __global__ __launch_bounds__(STEP_THREADS) void k_block_begin(const ChainTask *__restrict__ chains)
 {
-    __shared__ __align__(16) unsigned char lds[open_lds_bytes<STEP_THREADS>()];
+    extern __shared__ __align__(16) unsigned char lds[];
     block_open<STEP_THREADS>(chains[blockIdx.x], lds);
 }
 
 hipError_t launch_block_begin(const ChainTask *chains, int nchains, hipStream_t s)
 {
     if (nchains <= 0) return hipSuccess;
-    k_block_begin<<<nchains, STEP_THREADS, 0, s>>>(chains);
+    k_block_begin<<<nchains, STEP_THREADS, (uint32_t)open_lds_bytes<STEP_THREADS>(), s>>>(chains);
     return hipGetLastError();
 }
 
@@ -52,7 +52,7 @@ hipError_t launch_resolve_exact(const PointsView &P, double e2, const int32_t *c
 
 __global__ __launch_bounds__(STEP_THREADS) void k_accept(const ChainTask *__restrict__ chains)
 {
-    __shared__ __align__(16) unsigned char lds[accept_lds_bytes<STEP_THREADS>()];
+    extern __shared__ __align__(16) unsigned char lds[];
     block_accept<STEP_THREADS>(chains[blockIdx.x], lds);
 }
 
@@ -60,7 +60,7 @@ hipError_t launch_accept(const ChainTask *chains, int nchains, int maxB, hipStre
 {
     if (maxB > MAX_B) return hipErrorInvalidValue;
     if (nchains <= 0) return hipSuccess;
-    k_accept<<<nchains, STEP_THREADS, 0, s>>>(chains);
+    k_accept<<<nchains, STEP_THREADS, (uint32_t)accept_lds_bytes<STEP_THREADS>(), s>>>(chains);
     return hipGetLastError();
 }
 

@@ -16,7 +16,7 @@
 
 namespace bm {
 
-constexpr int MAX_B = 8192;
+constexpr int MAX_B = kMaxBlock;
 
 // LDS bytes the steps use (from a caller-provided, 16-byte aligned buffer).
 template <int NT> constexpr size_t open_lds_bytes()
@@ -30,13 +30,13 @@ template <int NT> constexpr size_t accept_lds_bytes()
 
 // Exclusive prefix of per-wave counts in (k, wave) order, for a workgroup whose
 // thread t holds items k * NT + t (k < MAX_B / NT): cnt[k] is this wave's count
-// of item row k (wave-uniform).  tab gets MAX_B / 64 + 1 ints: the bases, then
-// the total, which is returned; tab[k * NT / 64 + wave] is the wave's base.
+// of item row k (wave-uniform).  tab gets RUN * NT / 64 + 1 ints: the bases,
+// then the total, which is returned; tab[k * NT / 64 + wave] is the wave's base.
 template <int NT, int RUN>
 __device__ int slot_scan(const int (&cnt)[RUN], int *tab)
 {
     constexpr int NW = NT / 64, E = RUN * NW, PER = (E + 63) / 64;
-    static_assert(E == MAX_B / 64, "one entry per bitmap word");
+    static_assert(E <= MAX_B / 64, "at most one entry per bitmap word");
     const int lane = lane_id(), wid = (int)(threadIdx.x >> 6);
     __syncthreads();                                             // tab's previous use is over
     if (lane == 0) {
@@ -236,23 +236,18 @@ __device__ void block_open(const ChainTask &T, unsigned char *lds)
 // The accepted ranks go to A (the range pass's list), the landmark list
 // (original indices) and lm_rank at ordinal st->L, and the block is recorded
 // in blog[(st->blocks - 1) % kBlockLogSize].
-template <int NT>
-__device__ void block_accept(const ChainTask &T, unsigned char *lds)
+// The acceptance of a block of nc <= RUN * NT candidates.
+template <int NT, int RUN>
+__device__ void accept_run(const ChainTask &T, unsigned char *lds, BM_GLOBAL GreedyState *st, const int nc)
 {
     constexpr int NWAVES = NT / 64;
-    constexpr int RUN = MAX_B / NT;
+    static_assert(RUN <= 32 && RUN * NT <= MAX_B, "a thread's candidates fit one 32-bit mask");
     unsigned long long *acc = (unsigned long long *)lds;        // [MAX_B / 64] accepted
     unsigned long long *rej = acc + MAX_B / 64;                 // [MAX_B / 64] rejected
     int *sh_undecided = (int *)(rej + MAX_B / 64);
     int *tab = sh_undecided + 4;                                // [MAX_B / 64 + 4] slot bases
     int16_t *flist = (int16_t *)(tab + MAX_B / 64 + 4);         // [MAX_B] flagged rows
-    BM_GLOBAL GreedyState *st = gbl(T.st);
-    const int nc = st->nc;
     const int tid = (int)threadIdx.x;
-    if (nc == 0) {                                               // no block (the chain is done)
-        if (tid == 0) st->na = 0;
-        return;
-    }
     const int64_t L0 = st->L;
     const BM_GLOBAL uint64_t *C = gbl(T.C);
     const int nw = (T.B + 63) / 64;
@@ -381,6 +376,21 @@ __device__ void block_accept(const ChainTask &T, unsigned char *lds)
         b.m = st->m;
         b.nkeys_before = *gbl(T.nkeys);
     }
+}
+
+template <int NT>
+__device__ void block_accept(const ChainTask &T, unsigned char *lds)
+{
+    constexpr int RUN = MAX_B / NT;
+    BM_GLOBAL GreedyState *st = gbl(T.st);
+    const int nc = st->nc;
+    if (nc == 0) {                                               // no block (the chain is done)
+        if (threadIdx.x == 0) st->na = 0;
+        return;
+    }
+    // a block of at most half the largest size takes half the runs
+    if (nc <= MAX_B / 2) accept_run<NT, RUN / 2>(T, lds, st, nc);
+    else accept_run<NT, RUN>(T, lds, st, nc);
 }
 
 } // namespace bm

@@ -365,7 +365,7 @@ inline void check_common(const void *points, int64_t n, int32_t d, int32_t dtype
     if (n > 0 && !points) fail(BM_EINVAL, "points is NULL");
     if (o.path < BM_PATH_AUTO || o.path > BM_PATH_F16) fail(BM_EINVAL, "unknown path");
     if (o.refine != 0 && o.refine != 1) fail(BM_EINVAL, "refine must be 0 or 1");
-    if (o.block < 0 || o.block > 8192) fail(BM_EINVAL, "block must be 0 (automatic) or 1..8192");
+    if (o.block < 0 || o.block > kMaxBlock) fail(BM_EINVAL, "block must be 0 (automatic) or 1..16384");
     if (o.max_device_bytes < 0 || o.init_member_capacity < 0) fail(BM_EINVAL, "negative size option");
     if ((o.profile != 0 && o.profile != 1) || (o.no_graph != 0 && o.no_graph != 1))
         fail(BM_EINVAL, "profile and no_graph must be 0 or 1");
@@ -416,6 +416,17 @@ inline int64_t range_target_wg()
         return e ? atoll(e) : 0LL;
     }();
     return env_wg > 0 ? env_wg : 256;
+}
+// Workgroups of a candidate resolve (B x B pairs, half of them above the
+// diagonal and skipped): BM_RESOLVE_WORKGROUPS, else twice the range pass's
+// target, so that the workgroups left below the diagonal still fill the chip.
+inline int64_t resolve_target_wg()
+{
+    static const int64_t env_wg = [] {
+        const char *e = getenv("BM_RESOLVE_WORKGROUPS");
+        return e ? atoll(e) : 0LL;
+    }();
+    return env_wg > 0 ? env_wg : 2 * range_target_wg();
 }
 
 // A captured sequence of kernels replayed as one HIP graph.  Captured on a
@@ -507,7 +518,7 @@ inline int32_t tuned_block(int64_t n, int32_t d, bool batch)
     }
     if (!best) return 0;
     const int32_t B = batch ? best->batch : best->single;
-    return std::min<int32_t>(std::max<int32_t>(B, 1), 8192);
+    return std::min<int32_t>(std::max<int32_t>(B, 1), kMaxBlock);
 }
 
 inline int auto_block(int64_t n, int32_t d, int path)

@@ -74,7 +74,7 @@ def test_bad_arguments():
     x = np.zeros((4, 2))
     assert _code(lambda: bm.build(x, 1.0, order=[0, 1, 1, 2])) == bm.BM_EINVAL
     assert _code(lambda: bm.build(x, 1.0, order=[0, 1, 2, 4])) == bm.BM_EINVAL
-    assert _code(lambda: bm.build(x, 1.0, block=9000)) == bm.BM_EINVAL
+    assert _code(lambda: bm.build(x, 1.0, block=20000)) == bm.BM_EINVAL
     assert _code(lambda: bm.build(x, 1.0, path=9)) == bm.BM_EINVAL
     assert _code(lambda: bm.range_sets(x, [0, 4], 1.0)) == bm.BM_EINVAL
     lib = bm.load_library()

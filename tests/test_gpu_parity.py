@@ -71,7 +71,7 @@ def test_small_3d_config(path):
 
 
 @pytest.mark.parametrize("path", EXACT_PATHS)
-@pytest.mark.parametrize("B", [1, 7, 64, 300, 4096, 8192])
+@pytest.mark.parametrize("B", [1, 7, 64, 300, 4096, 8192, 16384])
 def test_block_sizes(path, B):
     x = W.clusters(3001, 5, k=6, box=3.0, seed=4, dtype=np.float32)
     say("clusters n=3001 d=5 eps=0.7", path, "B", B)
