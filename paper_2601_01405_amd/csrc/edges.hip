@@ -149,12 +149,15 @@ __device__ __forceinline__ void walk_union(int32_t i, int64_t m0, int64_t m1, co
         sh_s0[tid] = s0;
         __syncthreads();
         const int nm = (int)min<int64_t>(EP_THREADS, m1 - mc);
+        // entry e's member: the last one with offset <= e; e grows by
+        // EP_THREADS per step, so each thread advances its own cursor (a few
+        // members per step) instead of searching the offsets again
+        int lo = 0;
+        int64_t next_off = nm > 1 ? sh_off[1] : INT64_MAX;
         for (int64_t e = tid; e < tot; e += EP_THREADS) {
-            int lo = 0, hi = nm - 1;                            // last member with offset <= e
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (sh_off[mid] <= e) lo = mid;
-                else hi = mid - 1;
+            while (next_off <= e) {
+                ++lo;
+                next_off = lo + 1 < nm ? sh_off[lo + 1] : INT64_MAX;
             }
             const int32_t j = slist[sh_s0[lo] + (e - sh_off[lo])];
             if (j > i) visit(j);
@@ -167,11 +170,12 @@ __global__ __launch_bounds__(EP_THREADS) void k_edge_pass(int mode, const int32_
                                                           const int64_t *seg, int nseg, const int64_t *row_ptr,
                                                           const int32_t *member_idx, const int64_t *sptr,
                                                           const int32_t *slist, int64_t *deg, const int64_t *eptr,
-                                                          int32_t *edges)
+                                                          int32_t *edges, EdgeStore store)
 {
     __shared__ int32_t buf[EP_CAP];
     __shared__ unsigned long long bits[EP_WORDS];
     __shared__ int sh_cnt;
+    __shared__ int64_t sh_slot;
     __shared__ int64_t sh_scan[EP_THREADS / 64];
     __shared__ int64_t sh_off[EP_THREADS], sh_s0[EP_THREADS];
     const int32_t i = rows ? rows[blockIdx.x] : (int32_t)blockIdx.x;
@@ -249,17 +253,44 @@ __global__ __launch_bounds__(EP_THREADS) void k_edge_pass(int mode, const int32_
         }
         return;
     }
-    // bitmap over j in (i, jend) in chunks of EP_WORDS * 64 landmarks
+    // bitmap over j in (i, jend) in chunks of EP_WORDS * 64 landmarks.  The
+    // counting pass keeps the row's bitmap in a slot of `store` while slots
+    // last (slots[b] records which); the emitting pass reads a kept bitmap
+    // back instead of walking the union again.
+    const int b = (int)blockIdx.x;
+    if (tid == 0) {
+        int64_t slot = -1;
+        if (mode == 0) {
+            if (store.bits) {
+                const unsigned long long t = atomicAdd(store.count, 1ull);
+                if ((int64_t)t < store.cap) slot = (int64_t)t;
+            }
+            if (store.slots) store.slots[b] = (int32_t)slot;
+        } else if (store.slots) {
+            slot = store.slots[b];
+        }
+        sh_slot = slot;
+    }
+    __syncthreads();
+    uint64_t *kept = sh_slot >= 0 ? store.bits + sh_slot * store.words : nullptr;
     int64_t written = 0;
     for (int64_t base = (int64_t)i + 1; base < jend; base += (int64_t)EP_WORDS * 64) {
         const int64_t span = min((int64_t)EP_WORDS * 64, jend - base);
         const int nwords = (int)((span + 63) >> 6);
-        for (int t = tid; t < nwords; t += EP_THREADS) bits[t] = 0ull;
-        __syncthreads();
-        walk_union(i, m0, m1, member_idx, sptr, slist, sh_off, sh_s0, sh_scan, [&](int32_t j) {
-            const int64_t r = (int64_t)j - base;
-            if (r >= 0 && r < span) atomicOr(&bits[r >> 6], 1ull << (r & 63));
-        });
+        const int64_t wofs = (base - (int64_t)i - 1) >> 6;
+        if (mode == 1 && kept) {
+            for (int t = tid; t < nwords; t += EP_THREADS) bits[t] = kept[wofs + t];
+            __syncthreads();
+        } else {
+            for (int t = tid; t < nwords; t += EP_THREADS) bits[t] = 0ull;
+            __syncthreads();
+            walk_union(i, m0, m1, member_idx, sptr, slist, sh_off, sh_s0, sh_scan, [&](int32_t j) {
+                const int64_t r = (int64_t)j - base;
+                if (r >= 0 && r < span) atomicOr(&bits[r >> 6], 1ull << (r & 63));
+            });
+            if (mode == 0 && kept)
+                for (int t = tid; t < nwords; t += EP_THREADS) kept[wofs + t] = bits[t];
+        }
         const int per = (nwords + EP_THREADS - 1) / EP_THREADS;
         const int w0 = tid * per;
         int64_t mine = 0;
@@ -268,10 +299,10 @@ __global__ __launch_bounds__(EP_THREADS) void k_edge_pass(int mode, const int32_
         int64_t pos = block_excl_scan<EP_THREADS>(mine, &chunk_total, sh_scan);
         if (mode == 1) {
             for (int w = w0; w < w0 + per && w < nwords; ++w) {
-                unsigned long long b = bits[w];
-                while (b) {
-                    const int bit = __ffsll(b) - 1;
-                    b &= b - 1;
+                unsigned long long bb = bits[w];
+                while (bb) {
+                    const int bit = __ffsll(bb) - 1;
+                    bb &= bb - 1;
                     edges[2 * (out0 + written + pos)] = i;
                     edges[2 * (out0 + written + pos) + 1] = (int32_t)(base + (w << 6) + bit);
                     ++pos;
@@ -286,11 +317,12 @@ __global__ __launch_bounds__(EP_THREADS) void k_edge_pass(int mode, const int32_
 
 hipError_t launch_edge_pass(int mode, int64_t nrows, const int32_t *rows, int64_t L, const int64_t *seg, int nseg,
                             const int64_t *row_ptr, const int32_t *member_idx, const int64_t *sptr,
-                            const int32_t *slist, int64_t *deg, const int64_t *eptr, int32_t *edges, hipStream_t s)
+                            const int32_t *slist, int64_t *deg, const int64_t *eptr, int32_t *edges,
+                            const EdgeStore &store, hipStream_t s)
 {
     if (nrows <= 0) return hipSuccess;
     k_edge_pass<<<(unsigned)nrows, EP_THREADS, 0, s>>>(mode, rows, L, seg, nseg, row_ptr, member_idx, sptr, slist,
-                                                       deg, eptr, edges);
+                                                       deg, eptr, edges, store);
     return hipGetLastError();
 }
 

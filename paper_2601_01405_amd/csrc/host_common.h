@@ -760,16 +760,39 @@ inline int64_t edges_of(Device &dev, const uint64_t *skeys, int64_t M, int64_t L
     hip_ok(launch_edge_rows(skeys, M, bn, sptr, L, flag, rows, nrows_d, dev.s), "edge rows");
     const int64_t nrows = (int64_t)dev.fetch(nrows_d);
     dev.release(flag);
+    // bitmaps of the large rows kept between the two passes (at most 2 GiB,
+    // and a sixteenth of the device's memory)
+    EdgeStore store{};
+    const int64_t words = (L + 63) / 64;
+    size_t total_mem = 0;
+    if (hipDeviceTotalMem(&total_mem, dev.dev) != hipSuccess) total_mem = 0;
+    const int64_t budget = std::min<int64_t>((int64_t)1 << 31, (int64_t)(total_mem / 16));
+    store.cap = std::min<int64_t>(nrows, budget / (words * 8));
+    if (store.cap > 0) {
+        store.words = words;
+        store.bits = dev.alloc<uint64_t>((size_t)(store.cap * words));
+        store.count = dev.zeros<unsigned long long>(1);
+        store.slots = dev.alloc<int32_t>((size_t)std::max<int64_t>(nrows, 1));
+    } else {
+        store.cap = 0;
+    }
     int64_t *deg = dev.zeros<int64_t>((size_t)L);
-    hip_ok(launch_edge_pass(0, nrows, rows, L, seg, nseg, row_ptr, midx, sptr, slist, deg, nullptr, nullptr, dev.s),
+    hip_ok(launch_edge_pass(0, nrows, rows, L, seg, nseg, row_ptr, midx, sptr, slist, deg, nullptr, nullptr, store,
+                            dev.s),
            "edge count");
     int64_t *eptr = dev.alloc<int64_t>((size_t)L + 1);
     scan_into(dev, deg, eptr, L);
     const int64_t E = (int64_t)dev.fetch(eptr + L);
     *edges = dev.alloc<int32_t>((size_t)std::max<int64_t>(2 * E, 1));
     if (E > 0)
-        hip_ok(launch_edge_pass(1, nrows, rows, L, seg, nseg, row_ptr, midx, sptr, slist, deg, eptr, *edges, dev.s),
+        hip_ok(launch_edge_pass(1, nrows, rows, L, seg, nseg, row_ptr, midx, sptr, slist, deg, eptr, *edges, store,
+                                dev.s),
                "edge emit");
+    if (store.bits) {
+        dev.release(store.bits);
+        dev.release(store.count);
+        dev.release(store.slots);
+    }
     dev.release(deg);
     dev.release(rows);
     dev.release(slist);

@@ -89,9 +89,20 @@ hipError_t launch_edge_rows(const uint64_t *keys, int64_t M, int32_t bn, const i
 // number of neighbours j > i;  mode 1: write them at eptr[i].  seg[0..nseg]
 // (device, may be null) splits the rows into segments that share no column
 // (the chains of a batch), which bounds the neighbours of a row.
+// Row bitmaps the counting pass keeps for the emitting pass: `cap` slots of
+// `words` words (one bit per landmark past the row), claimed with *count (zero
+// at the start); slots[b] is the slot of the pass's workgroup b, or -1.  All
+// null: every row is walked twice.
+struct EdgeStore {
+    uint64_t *bits;
+    int64_t words, cap;
+    unsigned long long *count;
+    int32_t *slots;
+};
 hipError_t launch_edge_pass(int mode, int64_t nrows, const int32_t *rows, int64_t L, const int64_t *seg, int nseg,
                             const int64_t *row_ptr, const int32_t *member_idx, const int64_t *sptr,
-                            const int32_t *slist, int64_t *deg, const int64_t *eptr, int32_t *edges, hipStream_t s);
+                            const int32_t *slist, int64_t *deg, const int64_t *eptr, int32_t *edges,
+                            const EdgeStore &store, hipStream_t s);
 
 // ---- batches (batch.hip) ---------------------------------------------------------------------
 // Sorted chain-tagged keys (chain << (bl + bn) | ordinal << bn | index) into the
