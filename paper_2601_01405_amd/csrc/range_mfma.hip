@@ -324,7 +324,6 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
     const BM_GLOBAL int32_t *A = gbl(T.A);
     const RangeOut o = T.o;
     const SettledSet sd = T.sd;
-    const int NGW = T.NGW, chunks = T.chunks;
     const int S = CHUNKED ? a.S : KS;
     const int tile_vecs = S * 64;                                  // operand vectors of one tile
     const int buf_vecs = TPS * tile_vecs;
@@ -343,6 +342,16 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
     const int tid = (int)threadIdx.x;
     const int wid = tid >> 6, lane = lane_id(), col = lane & 31, half = lane >> 5;
     const int lb = (int)blockIdx.x - T.wg0;                        // workgroup within the task
+    // The launch is sized for a full block; its workgroups are spread over the
+    // landmark groups this pass actually has (fewer once candidates are
+    // rejected or a chain ends), in whole rounds of 8 (one per XCD).
+    const int launched = T.NGW * T.chunks;
+    const int NGW = max(1, min((na + RM_THREADS - 1) / RM_THREADS, launched / 8));
+    const int chunks = launched / NGW / 8 * 8;
+    if (lb >= NGW * chunks) {                                      // workgroup-uniform
+        range_wg_exit<CONFLICT>(T, clk, smem);
+        return;
+    }
     const int xcd = lb & 7;
     const int kk = lb >> 3;
     const int g = kk % NGW;
