@@ -42,6 +42,8 @@ struct GreedyState {
     unsigned long long accepted;    // blocks accepted (their block log entries are written)
     unsigned int ticket;            // workgroups of the running launch that have finished
     unsigned int pad2_;
+    int64_t settle_from;            // settled entries [settle_from, m) listed by the last
+                                    // opening (ranks in idx), copied by the next resolve
 };
 
 // Per-block record for recomputing a block's memberships after the key
@@ -60,7 +62,7 @@ struct BlockLog {
 struct SettledSet {
     uint16_t *Pop;                  // point-side operands, swizzled like MfmaArgs::Pop
     float *T3;                      // thresholds, tiled like MfmaArgs::T3
-    int32_t *idx;                   // original row index of entry j
+    int32_t *idx;                   // original row index of entry j (its rank until copied)
 };
 constexpr int kBlockLogSize = 256;
 

@@ -21,7 +21,7 @@ constexpr int MAX_B = kMaxBlock;
 // LDS bytes the steps use (from a caller-provided, 16-byte aligned buffer).
 template <int NT> constexpr size_t open_lds_bytes()
 {
-    return 16 + (size_t)NT / 64 * 4 + (size_t)NT * 16 + (size_t)MAX_B * 4;
+    return 16 + (size_t)NT / 64 * 4 + (size_t)MAX_B * 4;
 }
 template <int NT> constexpr size_t accept_lds_bytes()
 {
@@ -83,8 +83,7 @@ __device__ void block_open(const ChainTask &T, unsigned char *lds)
     int64_t *sh_cursor = (int64_t *)lds;
     int32_t *sh_first = (int32_t *)(lds + 8);
     int *sh_scan = (int *)(lds + 16);
-    int32_t *sel = (int32_t *)(lds + 16 + NT / 64 * 4);
-    int32_t *clist = sel + NT * 4;                               // [MAX_B] the gathered ranks
+    int32_t *clist = (int32_t *)(lds + 16 + NT / 64 * 4);       // [MAX_B] the gathered ranks
     const int tid = (int)threadIdx.x;
     BM_GLOBAL GreedyState *st = gbl(T.st);
     const int64_t n = T.n;
@@ -140,67 +139,44 @@ __device__ void block_open(const ChainTask &T, unsigned char *lds)
     for (int j = tid; j < count; j += NT) gbl(T.cand)[j] = clist[j];  // coalesced
 
     int64_t R1 = R0;
+    const int64_t m_old = m;
     if (T.settle && count > 0) {
-        // one bitmap word (64 ranks) per thread per round; the round's
-        // non-landmarks are listed in rank order, then their thresholds,
-        // indices and operands copied
-        const MfmaArgs &a = T.a;
-        const SettledSet &sd = T.sd;
+        // The non-landmarks among ranks [R0, R1) are listed in rank order:
+        // 64 ranks per thread per round into LDS (the gather's list, free
+        // again), then out to idx[m ..] coalesced.  The next resolve pass
+        // copies their thresholds, operands and original indices with all its
+        // workgroups (settle_copy).
         R1 = ((int64_t)*sh_first >> 5) << 5;
-        const int S = a.S, nvec = 2 * S;
-        constexpr int kSel = NT * 4;                             // listed per pass of the copy
+        int32_t *sel = clist;
+        constexpr int kSel = MAX_B;                              // listed per pass
+        const BM_GLOBAL uint64_t *islm = gbl(T.islm);
+        BM_GLOBAL int32_t *sidx = gbl(T.sd.idx);
         for (int64_t w0 = R0 >> 6; (w0 << 6) < R1; w0 += NT) {  // R0 is a multiple of 32
             const int64_t w = w0 + tid;
             uint64_t msk = 0;
             if ((w << 6) < R1) {
-                msk = ~gbl(T.islm)[w];
+                msk = ~islm[w];
                 const int64_t lo = w << 6;
                 if (lo < R0) msk &= (~0ull) << (R0 - lo);        // R0 - lo is 0 or 32
                 if (R1 - lo < 64) msk &= (1ull << (R1 - lo)) - 1;
             }
             int total;
             const int pre = block_excl_scan<NT>((int)__popcll(msk), &total, sh_scan);
-            // thresholds and indices straight away; operands through the LDS list
-            for (int k = pre; msk; ++k) {
-                const int b = __ffsll((unsigned long long)msk) - 1;
-                msk &= msk - 1;
-                const int64_t r = (w << 6) + b;
-                const int64_t j = m + k;
-#pragma unroll
-                for (int q = 0; q < 3; ++q) gbl(sd.T3)[t3_index(j, q)] = gbl(a.T3)[t3_index(r, q)];
-                gbl(sd.idx)[j] = T.perm ? gbl(T.perm)[r] : (int32_t)r;
-                if (k < kSel) sel[k] = (int32_t)r;
-            }
-            __syncthreads();
             for (int q0 = 0; q0 < total; q0 += kSel) {
-                if (q0 > 0) {                                    // a long round: list the next part again
-                    __syncthreads();
-                    int k = pre;
-                    uint64_t mm = 0;
-                    if ((w << 6) < R1) {
-                        mm = ~gbl(T.islm)[w];
-                        const int64_t lo = w << 6;
-                        if (lo < R0) mm &= (~0ull) << (R0 - lo);
-                        if (R1 - lo < 64) mm &= (1ull << (R1 - lo)) - 1;
-                    }
-                    for (; mm; ++k) {
+                {
+                    uint64_t mm = msk;
+                    for (int k = pre; mm; ++k) {
                         const int b = __ffsll((unsigned long long)mm) - 1;
                         mm &= mm - 1;
                         if (k >= q0 && k < q0 + kSel) sel[k - q0] = (int32_t)((w << 6) + b);
                     }
-                    __syncthreads();
                 }
+                __syncthreads();
                 const int cnt = min(kSel, total - q0);
-                for (int v = tid; v < cnt * nvec; v += NT) {
-                    const int q = v / nvec, rem = v - q * nvec, ss = rem >> 1, half = rem & 1;
-                    const int64_t src = sel[q], dst = m + q0 + q;
-                    const int64_t so = ((((src >> 5) * S + ss) * 64) + (src & 31) + 32 * half) * 8;
-                    const int64_t dof = ((((dst >> 5) * S + ss) * 64) + (dst & 31) + 32 * half) * 8;
-                    *(BM_GLOBAL u32x4 *)gbl(sd.Pop + dof) = *(const BM_GLOBAL u32x4 *)gbl(a.Pop + so);
-                }
+                for (int q = tid; q < cnt; q += NT) sidx[m + q0 + q] = sel[q];
+                __syncthreads();                                 // sel is listed again next
             }
             m += total;
-            __syncthreads();
         }
     }
 
@@ -218,8 +194,62 @@ __device__ void block_open(const ChainTask &T, unsigned char *lds)
             if (T.settle) {
                 st->rlo = R1;
                 st->m = m;
+                st->settle_from = m_old;
             }
         }
+    }
+}
+
+// Copy the entries [settle_from, m) the last opening of chain T listed (their
+// ranks in idx) into the settled set: thresholds, operands, original index.
+// Part `part` of `parts` workgroups takes a contiguous share; neighbouring
+// threads copy neighbouring entries, several loads in flight per thread.
+// Called by every workgroup of the resolve that follows the opening.
+template <int NT>
+__device__ void settle_copy(const ChainTask &T, int part, int parts)
+{
+    const BM_GLOBAL GreedyState *st = gbl(T.st);
+    if (!T.settle || st->nc == 0) return;                        // no block was opened
+    const int64_t e0 = st->settle_from, e1 = st->m;
+    const int64_t per = (e1 - e0 + parts - 1) / parts;
+    const int64_t a0 = e0 + (int64_t)part * per, a1 = min(e1, a0 + per);
+    if (a0 >= a1) return;
+    const int cnt = (int)(a1 - a0);
+    const MfmaArgs &a = T.a;
+    const int S = a.S, nvec = 2 * S;
+    const int tid = (int)threadIdx.x;
+    const BM_GLOBAL float *aT3 = gbl(a.T3);
+    BM_GLOBAL float *sT3 = gbl(T.sd.T3);
+    BM_GLOBAL int32_t *sidx = gbl(T.sd.idx);
+    const BM_GLOBAL int32_t *perm = gbl(T.perm);
+    const BM_GLOBAL u32x4 *aP = (const BM_GLOBAL u32x4 *)gbl(a.Pop);
+    BM_GLOBAL u32x4 *sP = (BM_GLOBAL u32x4 *)gbl(T.sd.Pop);
+    // operands first (they read the ranks in idx), vector sv = 2 K-step + half
+    // of entry q, entries fastest
+    const int nv = cnt * nvec;
+    for (int v0 = tid; v0 < nv; v0 += 4 * NT) {
+        u32x4 val[4];
+        int64_t dof[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int v = min(v0 + u * NT, nv - 1);
+            const int sv = v / cnt, q = v - sv * cnt;
+            const int ss = sv >> 1, half = sv & 1;
+            const int64_t src = sidx[a0 + q], dst = a0 + q;
+            val[u] = aP[(((src >> 5) * S + ss) * 64) + (src & 31) + 32 * half];
+            dof[u] = (((dst >> 5) * S + ss) * 64) + (dst & 31) + 32 * half;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (v0 + u * NT < nv) sP[dof[u]] = val[u];
+    }
+    __syncthreads();                                             // every rank in idx has been read
+    for (int q = tid; q < cnt; q += NT) {
+        const int64_t j = a0 + q;
+        const int32_t r = sidx[j];
+#pragma unroll
+        for (int c3 = 0; c3 < 3; ++c3) sT3[t3_index(j, c3)] = aT3[t3_index(r, c3)];
+        sidx[j] = T.perm ? perm[r] : r;
     }
 }
 

@@ -346,6 +346,9 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
     // landmark groups this pass actually has (fewer once candidates are
     // rejected or a chain ends), in whole rounds of 8 (one per XCD).
     const int launched = T.NGW * T.chunks;
+    // a resolve first copies its share of the entries the opening settled
+    // (the range pass after it reads them)
+    if (CONFLICT && T.chain) settle_copy<RM_THREADS>(*T.chain, lb, launched);
     const int NGW = max(1, min((na + RM_THREADS - 1) / RM_THREADS, launched / 8));
     const int chunks = launched / NGW / 8 * 8;
     if (lb >= NGW * chunks) {                                      // workgroup-uniform
