@@ -152,15 +152,25 @@ __device__ __forceinline__ void walk_union(int32_t i, int64_t m0, int64_t m1, co
         // entry e's member: the last one with offset <= e; e grows by
         // EP_THREADS per step, so each thread advances its own cursor (a few
         // members per step) instead of searching the offsets again
+        // (four entries per step: their loads are all in flight before the
+        // first visit; the last step reads in-bounds repeats it ignores)
         int lo = 0;
         int64_t next_off = nm > 1 ? sh_off[1] : INT64_MAX;
-        for (int64_t e = tid; e < tot; e += EP_THREADS) {
-            while (next_off <= e) {
-                ++lo;
-                next_off = lo + 1 < nm ? sh_off[lo + 1] : INT64_MAX;
+        constexpr int U = 4;
+        for (int64_t e = tid; e < tot; e += U * EP_THREADS) {
+            int32_t jv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t eu = min(e + (int64_t)u * EP_THREADS, tot - 1);
+                while (next_off <= eu) {
+                    ++lo;
+                    next_off = lo + 1 < nm ? sh_off[lo + 1] : INT64_MAX;
+                }
+                jv[u] = slist[sh_s0[lo] + (eu - sh_off[lo])];
             }
-            const int32_t j = slist[sh_s0[lo] + (e - sh_off[lo])];
-            if (j > i) visit(j);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (e + (int64_t)u * EP_THREADS < tot && jv[u] > i) visit(jv[u]);
         }
         __syncthreads();
     }
