@@ -152,11 +152,11 @@ __device__ __forceinline__ void walk_union(int32_t i, int64_t m0, int64_t m1, co
         // entry e's member: the last one with offset <= e; e grows by
         // EP_THREADS per step, so each thread advances its own cursor (a few
         // members per step) instead of searching the offsets again
-        // (four entries per step: their loads are all in flight before the
+        // (eight entries per step: their loads are all in flight before the
         // first visit; the last step reads in-bounds repeats it ignores)
         int lo = 0;
         int64_t next_off = nm > 1 ? sh_off[1] : INT64_MAX;
-        constexpr int U = 4;
+        constexpr int U = 8;
         for (int64_t e = tid; e < tot; e += U * EP_THREADS) {
             int32_t jv[U];
 #pragma unroll
