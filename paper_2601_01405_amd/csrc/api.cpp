@@ -105,7 +105,7 @@ bm_result *run_job(const Job &job, const bm_options &o)
             }
         }
         res->stats.path = path;
-        const int B = o.block ? o.block : auto_block(n, d, path);
+        int B = o.block ? o.block : auto_block(n, d, path);
 
         // -- path preparation
         Fp32Thresholds thr32{};
@@ -125,17 +125,21 @@ bm_result *run_job(const Job &job, const bm_options &o)
 
         // -- range passes
         const auto t_greedy = clk::now();
-        res->stats.block = B;
         const int32_t bn = std::max(1, bitlen((uint64_t)std::max<int64_t>(n - 1, 1)));
         unsigned long long cap = o.init_member_capacity
                                      ? (unsigned long long)o.init_member_capacity
                                      : (unsigned long long)std::max<int64_t>(2 * n, 1 << 16);
-        if (!o.init_member_capacity && ma.Pop && !job.fixed && n >= kProbePoints) {
+        if ((!o.init_member_capacity || !o.block) && ma.Pop && !job.fixed && n >= kProbePoints) {
             // big clouds: the mean ball of 64 sampled landmarks sizes the buffer for
-            // the first blocks, so that they need no recompute after an overflow
+            // the first blocks, so that they need no recompute after an overflow,
+            // and with large balls (many candidates rejected, many members per
+            // pass) an automatic block is smaller
             const double ball = sample_pass(dev, P, ma, e2, 64).ball_mean;
-            cap = std::max<unsigned long long>(cap, (unsigned long long)(1.5 * ball * 4.0 * B) + 65536ull);
+            if (!o.block && ball >= kLargeBall) B = std::min(B, kLargeBallBlock);
+            if (!o.init_member_capacity)
+                cap = std::max<unsigned long long>(cap, (unsigned long long)(1.5 * ball * 4.0 * B) + 65536ull);
         }
+        res->stats.block = B;
         uint64_t *keys = dev.alloc<uint64_t>(cap);
         GreedyState *st = dev.zeros<GreedyState>(1);
         const int64_t lm_cap = std::max<int64_t>(job.fixed ? job.n_fixed : n, 1);
