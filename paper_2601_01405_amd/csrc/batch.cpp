@@ -54,6 +54,13 @@ struct Carve {
 
 // Workgroups per chain: about one per 1024 points, 8 to 256.
 int64_t chain_target_wg(int64_t n) { return std::max<int64_t>(8, std::min<int64_t>(256, n / 1024)); }
+// A chain's resolve: about 256 panel-tile products per workgroup over the
+// lower triangle of the B x B candidate matrix ((B/32)^2 / 2 of them), so that
+// the per-workgroup set-up is amortised; at least one round of 8.
+int64_t resolve_target_wg_of(int64_t B)
+{
+    return std::max<int64_t>(8, std::min<int64_t>(256, B * B / (1 << 19)));
+}
 
 } // namespace
 
@@ -338,7 +345,7 @@ void run_batch(const std::vector<const bm_problem *> &probs, const std::vector<i
                 v.c32_stride = 2 * nw;
                 v.rowflag = k.rowflag;
                 v.chain = ctask + c;
-                range_grid(k.B, k.B, std::max<int64_t>(8, std::min<int64_t>(256, k.B / 16)), &v.NGW, &v.chunks);
+                range_grid(k.B, k.B, resolve_target_wg_of(k.B), &v.NGW, &v.chunks);
                 v.wg0 = (int32_t)cl.qwg;
                 cl.qwg += (int64_t)v.NGW * v.chunks;
                 qmap.insert(qmap.end(), (size_t)v.NGW * v.chunks, (int32_t)qts.size());
