@@ -328,7 +328,11 @@ struct Device {
                 return;
             }
     }
-    void sync() { hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize"); }
+    void sync()
+    {
+        hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize");
+        up_used = 0;
+    }
     // Pinned host memory: [0, 4 KB) staging of small reads and block tables,
     // [4 KB, kPinnedBytes) staging of uploads.  Both wait for their copy.
     template <class T> T fetch(const T *dptr)
@@ -340,17 +344,21 @@ struct Device {
         std::memcpy(&v, (char *)pinned + 2048, sizeof(T));
         return v;
     }
+    // Uploads take consecutive pieces of the staging area and do not wait; the
+    // stream is drained only when the area is full (every wait drains it, so
+    // each one frees the whole area).
     void upload(void *dptr, const void *src, size_t bytes)
     {
         for (size_t off = 0; off < bytes; off += kUploadStage) {
             const size_t m = std::min(kUploadStage, bytes - off);
-            sync();                                     // the staging area is free again
-            std::memcpy((char *)pinned + 4096, (const char *)src + off, m);
-            hip_ok(hipMemcpyAsync((char *)dptr + off, (char *)pinned + 4096, m, hipMemcpyHostToDevice, s),
-                   "hipMemcpyAsync H2D");
+            if (up_used + m > kUploadStage) sync();
+            char *stage = (char *)pinned + 4096 + up_used;
+            std::memcpy(stage, (const char *)src + off, m);
+            hip_ok(hipMemcpyAsync((char *)dptr + off, stage, m, hipMemcpyHostToDevice, s), "hipMemcpyAsync H2D");
+            up_used += (m + 255) / 256 * 256;
         }
-        sync();
     }
+    size_t up_used = 0;                                 // staging bytes in use since the last wait
 };
 
 // ---- argument checks that need no device ----------------------------------------------

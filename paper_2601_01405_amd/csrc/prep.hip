@@ -35,28 +35,43 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long *slot, doub
     atomicMax(slot, (unsigned long long)__double_as_longlong(v));
 }
 
+// Grid-stride over the points; the maxima are reduced per workgroup first, so
+// that only two atomics per workgroup reach the two counters (atomics on one
+// address are serialised).
+constexpr int PS_THREADS = 256;
 template <int DT>
-__global__ void k_point_stats(PointsView P, double *nu, unsigned long long *stats)
+__global__ __launch_bounds__(PS_THREADS) void k_point_stats(PointsView P, double *nu, unsigned long long *stats)
 {
-    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    double s = 0.0, mabs = 0.0;
-    if (r < P.n) {
+    __shared__ double sh[2][PS_THREADS / 64];
+    double smax = 0.0, mabs = 0.0;
+    for (int64_t r = blockIdx.x * (int64_t)PS_THREADS + threadIdx.x; r < P.n; r += (int64_t)gridDim.x * PS_THREADS) {
         const int64_t o = orig_index(P, r) * (int64_t)P.d;
+        double s = 0.0;
         for (int32_t k = 0; k < P.d; ++k) {
             double v = load_coord<DT>(P.X, o + k);
             s = __fma_rn(v, v, s);
             mabs = fmax(mabs, fabs(v));
         }
-        nu[r] = s;
+        gbl(nu)[r] = s;
+        smax = fmax(smax, s);
     }
-    // wave maxima, then one atomic per wave
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
-        s = fmax(s, __shfl_xor(s, off, 64));
+        smax = fmax(smax, __shfl_xor(smax, off, 64));
         mabs = fmax(mabs, __shfl_xor(mabs, off, 64));
     }
+    const int wid = (int)(threadIdx.x >> 6);
     if (lane_id() == 0) {
-        atomic_max_nonneg(&stats[0], s);
+        sh[0][wid] = smax;
+        sh[1][wid] = mabs;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < PS_THREADS / 64; ++w) {
+            smax = fmax(smax, sh[0][w]);
+            mabs = fmax(mabs, sh[1][w]);
+        }
+        atomic_max_nonneg(&stats[0], smax);
         atomic_max_nonneg(&stats[1], mabs);
     }
 }
@@ -64,10 +79,11 @@ __global__ void k_point_stats(PointsView P, double *nu, unsigned long long *stat
 hipError_t launch_point_stats(const PointsView &P, double *nu, unsigned long long *stats, hipStream_t s)
 {
     if (P.n <= 0) return hipSuccess;
-    int blocks = (int)((P.n + 255) / 256);
-    if (P.dtype == 0) k_point_stats<0><<<blocks, 256, 0, s>>>(P, nu, stats);
-    else if (P.dtype == 1) k_point_stats<1><<<blocks, 256, 0, s>>>(P, nu, stats);
-    else k_point_stats<2><<<blocks, 256, 0, s>>>(P, nu, stats);
+    int64_t blocks = (P.n + PS_THREADS - 1) / PS_THREADS;
+    if (blocks > 1024) blocks = 1024;
+    if (P.dtype == 0) k_point_stats<0><<<(int)blocks, PS_THREADS, 0, s>>>(P, nu, stats);
+    else if (P.dtype == 1) k_point_stats<1><<<(int)blocks, PS_THREADS, 0, s>>>(P, nu, stats);
+    else k_point_stats<2><<<(int)blocks, PS_THREADS, 0, s>>>(P, nu, stats);
     return hipGetLastError();
 }
 
