@@ -430,7 +430,17 @@ bm_result *run_job(const Job &job, const bm_options &o)
                     upload_tasks();                 // the greedy's pass writes to the new buffer
                 }
                 if (hs.done) break;
-                batch = nbatch == 1 ? 3 : nbatch == 2 ? 8 : std::min(batch * 2, 64);   // graphs: multiples of 8
+                // the next batch: the blocks the progress so far predicts for the
+                // ranks left (10% more, at least 3, at most 64), so that few batches
+                // (host round trips) are needed; graphs take multiples of 8
+                {
+                    const double done_ranks = (double)std::max<int64_t>(hs.cursor, 1);
+                    const double left = (double)(n - hs.cursor) * (double)hs.blocks / done_ranks;
+                    int want = (int)std::ceil(1.1 * left) + 1;
+                    want = std::max(3, std::min(want, 64));
+                    if (use_graph && nbatch >= 2) want = (want + kGraphBlocks - 1) / kGraphBlocks * kGraphBlocks;
+                    batch = want;
+                }
             }
             L = hs.L;
             res->stats.blocks = (int64_t)hs.blocks;
