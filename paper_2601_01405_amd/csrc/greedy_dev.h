@@ -29,20 +29,16 @@ template <int NT> constexpr size_t accept_lds_bytes()
 }
 
 // Exclusive prefix of per-wave counts in (k, wave) order, for a workgroup whose
-// thread t holds items k * NT + t (k < MAX_B / NT): cnt[k] is this wave's count
-// of item row k (wave-uniform).  tab gets RUN * NT / 64 + 1 ints: the bases,
-// then the total, which is returned; tab[k * NT / 64 + wave] is the wave's base.
+// thread t holds items k * NT + t (k < RUN).  Before the call, lane 0 of each
+// wave has written its count of item row k to tab[k * NT / 64 + wave] (after a
+// barrier that ended tab's previous use).  On return tab holds the bases,
+// tab[RUN * NT / 64] the total, which is returned.
 template <int NT, int RUN>
-__device__ int slot_scan(const int (&cnt)[RUN], int *tab)
+__device__ int slot_scan(int *tab)
 {
     constexpr int NW = NT / 64, E = RUN * NW, PER = (E + 63) / 64;
     static_assert(E <= MAX_B / 64, "at most one entry per bitmap word");
     const int lane = lane_id(), wid = (int)(threadIdx.x >> 6);
-    __syncthreads();                                             // tab's previous use is over
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < RUN; ++k) tab[k * NW + wid] = cnt[k];
-    }
     __syncthreads();
     if (wid == 0) {
         int v[PER], sum = 0;
@@ -285,25 +281,21 @@ __device__ void accept_run(const ChainTask &T, unsigned char *lds, BM_GLOBAL Gre
     // Candidate j = k * NT + tid: the 64 lanes of a wave hold 64 consecutive
     // candidates, one bitmap word, so loads and stores coalesce and a ballot
     // is that word.  Rows with no earlier conflict are accepted at once.
-    int32_t rank[RUN];
     uint32_t flagged = 0, inrun = 0;
-    // (unconditional loads, clamped into the block, so that all of them are
-    // in flight at once instead of one wait per branch)
-    int fl[RUN];
+    {
+        // (unconditional loads, clamped into the block, so that all of them
+        // are in flight at once instead of one wait per branch)
+        int fl[RUN];
 #pragma unroll
-    for (int k = 0; k < RUN; ++k) {
-        const int jc = min(k * NT + tid, nc - 1);
-        fl[k] = gbl(T.rowflag)[jc];
-        rank[k] = gbl(T.cand)[jc];
-    }
+        for (int k = 0; k < RUN; ++k) fl[k] = gbl(T.rowflag)[min(k * NT + tid, nc - 1)];
 #pragma unroll
-    for (int k = 0; k < RUN; ++k) {
-        if (k * NT + tid < nc) {
-            inrun |= 1u << k;
-            if (fl[k]) flagged |= 1u << k;
+        for (int k = 0; k < RUN; ++k) {
+            if (k * NT + tid < nc) {
+                inrun |= 1u << k;
+                if (fl[k]) flagged |= 1u << k;
+            }
         }
     }
-    int cnt[RUN];
 #pragma unroll
     for (int k = 0; k < RUN; ++k) {
         const bool in = (inrun >> k) & 1u, f = (flagged >> k) & 1u;
@@ -312,11 +304,11 @@ __device__ void accept_run(const ChainTask &T, unsigned char *lds, BM_GLOBAL Gre
         if (lane == 0) {
             acc[k * NWAVES + wid] = okb;
             rej[k * NWAVES + wid] = 0ull;
+            tab[k * NWAVES + wid] = (int)__popcll(fb);
         }
-        cnt[k] = (int)__popcll(fb);
     }
     // the flagged rows in rank order
-    const int F = slot_scan<NT, RUN>(cnt, tab);
+    const int F = slot_scan<NT, RUN>(tab);
 #pragma unroll
     for (int k = 0; k < RUN; ++k) {
         const unsigned long long fb = __ballot((flagged >> k) & 1u);
@@ -371,7 +363,10 @@ __device__ void accept_run(const ChainTask &T, unsigned char *lds, BM_GLOBAL Gre
         const int j = k * NT + tid;
         if (((inrun >> k) & 1u) && ((acc[j >> 6] >> (j & 63)) & 1ull)) took |= 1u << k;
     }
-    int32_t orig[RUN];
+    // (the ranks are read again here, not held through the rounds)
+    int32_t rank[RUN], orig[RUN];
+#pragma unroll
+    for (int k = 0; k < RUN; ++k) rank[k] = gbl(T.cand)[min(k * NT + tid, nc - 1)];
     if (T.perm) {                                                // (unconditional loads: all in flight)
 #pragma unroll
         for (int k = 0; k < RUN; ++k) orig[k] = gbl(T.perm)[rank[k]];
@@ -379,9 +374,13 @@ __device__ void accept_run(const ChainTask &T, unsigned char *lds, BM_GLOBAL Gre
 #pragma unroll
         for (int k = 0; k < RUN; ++k) orig[k] = rank[k];
     }
+    __syncthreads();                                             // the rounds' reads of tab are over
 #pragma unroll
-    for (int k = 0; k < RUN; ++k) cnt[k] = (int)__popcll(__ballot((took >> k) & 1u));
-    const int total = slot_scan<NT, RUN>(cnt, tab);
+    for (int k = 0; k < RUN; ++k) {
+        const int c = (int)__popcll(__ballot((took >> k) & 1u));
+        if (lane == 0) tab[k * NWAVES + wid] = c;
+    }
+    const int total = slot_scan<NT, RUN>(tab);
 #pragma unroll
     for (int k = 0; k < RUN; ++k) {
         const unsigned long long tb = __ballot((took >> k) & 1u);
