@@ -226,11 +226,20 @@ constexpr int RM_WAVES = 8;
 constexpr int RM_THREADS = RM_WAVES * 64;
 constexpr int RM_MP = 2;
 
-// Tiles per LDS stage (16-32 KB of operands per stage); one tile when the
-// K steps are processed in chunks of 8.
+// Tiles per LDS stage (16-55 KB of operands per stage); one tile when the
+// K steps are processed in chunks of 8.  From K = 48 (three steps) on, except
+// at four steps where the LDS does not allow it, a stage holds twice the tiles
+// of the two-register-set scheme and is staged through one register set: the
+// next stage's loads have a whole (long) stage to arrive, and the workgroup
+// meets at half as many barriers.
+__host__ __device__ constexpr int stage_tiles_two_sets(int ks)
+{
+    return ks <= 2 ? 16 : ks <= 4 ? 8 : ks <= 6 ? 4 : 2;
+}
+__host__ __device__ constexpr bool one_set(bool chunked, int ks) { return !chunked && ks >= 3 && ks != 4; }
 __host__ __device__ constexpr int stage_tiles(bool chunked, int ks)
 {
-    return chunked ? 1 : (ks <= 2 ? 16 : ks <= 4 ? 8 : ks <= 6 ? 4 : 2);
+    return chunked ? 1 : one_set(chunked, ks) ? 2 * stage_tiles_two_sets(ks) : stage_tiles_two_sets(ks);
 }
 // Operand vectors of one stage, and per thread.
 __host__ __device__ constexpr int stage_vecs(bool chunked, int ks)
@@ -577,10 +586,11 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
     // One stage: store its staged loads to LDS buffer `buf`, start the loads of
     // the stage two ahead into the same registers, multiply the stage.
     int si = 0;                                                      // stage index (uniform)
+    constexpr bool kOneSet = one_set(CHUNKED, KS);
     auto run_stage = [&](int ts, int buf, u32x4 (&pre)[OPS], u32x4 &pre_t) {
         lstore(buf, pre, pre_t);
         __syncthreads();
-        gload(ts + 2 * TPS, pre, pre_t);
+        gload(ts + (kOneSet ? 1 : 2) * TPS, pre, pre_t);
         if (!CONFLICT) {
             const bool flush = kst_seen[(si + 1) & 1] >= kKeyStage / 2;   // slot (si - 1) & 1: uniform
             if (flush) flush_keys();
@@ -758,18 +768,30 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
         }
       }
     };
-    gload(t0, preA, pretA);
-    __builtin_amdgcn_sched_barrier(0);           // issue set A before set B: the waits rely on the order
-    gload(t0 + TPS, preB, pretB);
-    // Unrolled by two (distinct registers), with the odd last stage after the
-    // loop: every path into a stage has the set it stores as the older one in flight.
-    int ts = t0;
-    while (ts + TPS < t1) {
-        run_stage(ts, 0, preA, pretA);
-        run_stage(ts + TPS, 1, preB, pretB);
-        ts += 2 * TPS;
+    if constexpr (kOneSet) {
+        // one register set: a stage stores what the previous one loaded
+        gload(t0, preA, pretA);
+        int ts = t0;
+        while (ts + TPS < t1) {
+            run_stage(ts, 0, preA, pretA);
+            run_stage(ts + TPS, 1, preA, pretA);
+            ts += 2 * TPS;
+        }
+        if (ts < t1) run_stage(ts, 0, preA, pretA);
+    } else {
+        gload(t0, preA, pretA);
+        __builtin_amdgcn_sched_barrier(0);       // issue set A before set B: the waits rely on the order
+        gload(t0 + TPS, preB, pretB);
+        // Unrolled by two (distinct registers), with the odd last stage after the
+        // loop: every path into a stage has the set it stores as the older one in flight.
+        int ts = t0;
+        while (ts + TPS < t1) {
+            run_stage(ts, 0, preA, pretA);
+            run_stage(ts + TPS, 1, preB, pretB);
+            ts += 2 * TPS;
+        }
+        if (ts < t1) run_stage(ts, 0, preA, pretA);
     }
-    if (ts < t1) run_stage(ts, 0, preA, pretA);
     if (!CONFLICT && live) flush_queue();
     if (!CONFLICT) flush_keys();
     band = wave_sum(band);
