@@ -579,10 +579,6 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
         if (tid == 0) *kst_n = 0;
         __syncthreads();
     };
-    // Let the setup loads (A operands, accumulator starts) land before the loop,
-    // so the only loads in flight inside it are the next stage's staging loads
-    // and the waitcnt pass need not wait for them before the matrix ops.
-    __builtin_amdgcn_s_waitcnt(0);
     // One stage: store its staged loads to LDS buffer `buf`, start the loads of
     // the stage two ahead into the same registers, multiply the stage.
     int si = 0;                                                      // stage index (uniform)
@@ -768,9 +764,14 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
         }
       }
     };
+    // The first stage's loads go out with the setup loads (A operands,
+    // accumulator starts); then everything lands before the loop, so the only
+    // loads in flight inside it are staging loads and the waitcnt pass need
+    // not wait for them before the matrix ops.
     if constexpr (kOneSet) {
         // one register set: a stage stores what the previous one loaded
         gload(t0, preA, pretA);
+        __builtin_amdgcn_s_waitcnt(0);
         int ts = t0;
         while (ts + TPS < t1) {
             run_stage(ts, 0, preA, pretA);
@@ -780,6 +781,7 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
         if (ts < t1) run_stage(ts, 0, preA, pretA);
     } else {
         gload(t0, preA, pretA);
+        __builtin_amdgcn_s_waitcnt(0);
         __builtin_amdgcn_sched_barrier(0);       // issue set A before set B: the waits rely on the order
         gload(t0 + TPS, preB, pretB);
         // Unrolled by two (distinct registers), with the odd last stage after the
