@@ -202,7 +202,7 @@ void run_batch(const std::vector<const bm_problem *> &probs, const std::vector<i
             c.B = o.block ? o.block : batch_block(q.n, q.d, q.path);
             const int64_t nwords = (q.n + 63) / 64, np = (q.n + 31) / 32 * 32;
             const int nw = (c.B + 63) / 64;
-            c.z_off = cz.take(sizeof(GreedyState));
+            c.z_off = cz.off;                                       // (states: one array of their own)
             cz.take(nwords * 8);                                    // covered
             if (settle) {
                 cz.take(nwords * 8);                                // islm
@@ -224,15 +224,18 @@ void run_batch(const std::vector<const bm_problem *> &probs, const std::vector<i
         }
     }
     const int nch = (int)ch.size();
+    // the chains' states side by side, so that one copy reads them all back
+    GreedyState *states = dev.alloc<GreedyState>((size_t)std::max(nch, 1));
     unsigned char *zero_arena = (unsigned char *)dev.raw_alloc(cz.off, true);
     unsigned char *inf_arena = ci.off ? (unsigned char *)dev.raw_alloc(ci.off, true) : nullptr;
     unsigned char *plain_arena = (unsigned char *)dev.raw_alloc(cp.off, true);
-    for (Chain &c : ch) {
+    for (size_t k = 0; k < ch.size(); ++k) {
+        Chain &c = ch[k];
         const Prob &q = pv[(size_t)c.p];
         const int64_t nwords = (q.n + 63) / 64, np = (q.n + 31) / 32 * 32;
         const int nw = (c.B + 63) / 64;
         Carve z{c.z_off}, i{c.i_off}, pl{c.p_off};
-        c.st = (GreedyState *)(zero_arena + z.take(sizeof(GreedyState)));
+        c.st = states + k;
         c.covered = (uint64_t *)(zero_arena + z.take(nwords * 8));
         if (settle) {
             c.islm = (uint64_t *)(zero_arena + z.take(nwords * 8));
@@ -369,6 +372,7 @@ void run_batch(const std::vector<const bm_problem *> &probs, const std::vector<i
     std::vector<GreedyState> sts((size_t)nch);
     auto run_all = [&]() {
         hip_ok(hipMemsetAsync(zero_arena, 0, cz.off, dev.s), "zero arena");
+        hip_ok(hipMemsetAsync(states, 0, (size_t)nch * sizeof(GreedyState), dev.s), "zero states");
         if (inf_arena)
             hip_ok(hipMemsetD32Async((hipDeviceptr_t)inf_arena, 0x7f800000, ci.off / 4, dev.s), "fill +inf");
         hip_ok(hipMemsetAsync(counters, 0, 16, dev.s), "zero counters");
@@ -401,9 +405,8 @@ void run_batch(const std::vector<const bm_problem *> &probs, const std::vector<i
             if (steps > nmax + 2 * kGraphSteps) fail(BM_EINTERNAL, "a chain did not finish");
             reps = std::min(reps * 2, 8);
         }
-        for (int c = 0; c < nch; ++c)
-            hip_ok(hipMemcpyAsync(&sts[(size_t)c], ch[(size_t)c].st, sizeof(GreedyState), hipMemcpyDeviceToHost, dev.s),
-                   "state D2H");
+        hip_ok(hipMemcpyAsync(sts.data(), states, (size_t)nch * sizeof(GreedyState), hipMemcpyDeviceToHost, dev.s),
+               "state D2H");
         dev.sync();
         return dev.fetch(counters);
     };
