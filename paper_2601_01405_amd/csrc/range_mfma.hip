@@ -631,16 +631,19 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
 
         const float tcut = thr[thr_off + col];
         bool cov = false, slow = false;
+        // Fast path: is any pair of the tile possibly a member?  (u, v:
+        // conservative thresholds for this point and panel; U, V and aw carry
+        // the slack for these two roundings; +inf for padding points.)  The
+        // BF16 paths ask it once for both panels (one ballot, one branch); the
+        // F16 paths, whose bands are wider, ask it panel by panel.
+        bool phit[RM_MP] = {};                                           // per panel (lane)
+        if constexpr (!F16) {
+            bool hit = false;
 #pragma unroll
-        for (int pi = 0; pi < RM_MP; ++pi) {
-            const int abase = (pbase + pi) * 32;
-            if (abase >= na) break;                                      // wave-uniform
-            const f32x16 av = acc[pi];
-            {
-                // fast path: is any pair of the 32x32 tile possibly a member?
-                // u, v: conservative thresholds for this point and panel (U, V and aw
-                // carry the slack for these two roundings); +inf for padding points
-                const float cut = a.refine ? tcut - aw[pi] : tcut;
+            for (int pi = 0; pi < RM_MP; ++pi) {
+                phit[pi] = false;
+                if ((pbase + pi) * 32 >= na) break;                      // wave-uniform
+                const f32x16 av = acc[pi];
                 float m = fmaxf(fmaxf(av[0], av[1]), av[2]);
                 m = fmaxf(fmaxf(m, av[3]), av[4]);
                 m = fmaxf(fmaxf(m, av[5]), av[6]);
@@ -649,7 +652,47 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
                 m = fmaxf(fmaxf(m, av[11]), av[12]);
                 m = fmaxf(fmaxf(m, av[13]), av[14]);
                 m = fmaxf(m, av[15]);
-                if (!__ballot(!(m <= cut))) {
+                phit[pi] = !(m <= (a.refine ? tcut - aw[pi] : tcut));
+                hit = hit || phit[pi];
+            }
+            if (!__ballot(hit)) {                                        // wave-uniform
+                if (CONFLICT) {
+                    // no pair of the tile conflicts: a zero word for every
+                    // candidate past a panel's first row (the words a row reads;
+                    // the others are masked or never read)
+                    const int64_t p = (int64_t)t * 32 + col;
+#pragma unroll
+                    for (int pi = 0; pi < RM_MP; ++pi) {
+                        const int abase = (pbase + pi) * 32;
+                        if (abase >= na) break;
+                        if (half == 0 && p < n && abase < p) gbl(T.C32)[p * T.c32_stride + (pbase + pi)] = 0u;
+                    }
+                }
+                continue;
+            }
+        }
+#pragma unroll
+        for (int pi = 0; pi < RM_MP; ++pi) {
+            const int abase = (pbase + pi) * 32;
+            if (abase >= na) break;                                      // wave-uniform
+            const f32x16 av = acc[pi];
+            {
+                // this panel alone: no possible member
+                bool ph;
+                if constexpr (!F16) {
+                    ph = phit[pi];
+                } else {
+                    float m = fmaxf(fmaxf(av[0], av[1]), av[2]);
+                    m = fmaxf(fmaxf(m, av[3]), av[4]);
+                    m = fmaxf(fmaxf(m, av[5]), av[6]);
+                    m = fmaxf(fmaxf(m, av[7]), av[8]);
+                    m = fmaxf(fmaxf(m, av[9]), av[10]);
+                    m = fmaxf(fmaxf(m, av[11]), av[12]);
+                    m = fmaxf(fmaxf(m, av[13]), av[14]);
+                    m = fmaxf(m, av[15]);
+                    ph = !(m <= (a.refine ? tcut - aw[pi] : tcut));
+                }
+                if (!__ballot(ph)) {
                     if (CONFLICT) {
                         // no pair of the tile conflicts: a zero word for every
                         // candidate past the panel's first row (the words a row
