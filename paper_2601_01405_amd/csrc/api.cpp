@@ -133,9 +133,11 @@ bm_result *run_job(const Job &job, const bm_options &o)
             // big clouds: the mean ball of 64 sampled landmarks sizes the buffer for
             // the first blocks, so that they need no recompute after an overflow,
             // and with large balls (many candidates rejected, many members per
-            // pass) an automatic block is smaller
+            // pass) an automatic block is smaller, with balls of about one point
+            // (every candidate accepted) larger
             const double ball = sample_pass(dev, P, ma, e2, 64).ball_mean;
             if (!o.block && ball >= kLargeBall) B = std::min(B, kLargeBallBlock);
+            if (!o.block && ball < kTinyBall) B = std::max(B, kTinyBallBlock);
             if (!o.init_member_capacity)
                 cap = std::max<unsigned long long>(cap, (unsigned long long)(1.5 * ball * 4.0 * B) + 65536ull);
         }

@@ -481,7 +481,9 @@ constexpr int kGraphBlocks = 8;                     // greedy blocks per capture
 constexpr int64_t kGraphMaxPoints = 1 << 17;        // single builds replay graphs below this size
 constexpr int64_t kProbePoints = 1 << 17;           // single builds from this size sample ball sizes
 constexpr double kLargeBall = 512.0;                // sampled mean ball from which an automatic
-constexpr int kLargeBallBlock = 2048;               // block is at most this size
+constexpr int kLargeBallBlock = 2048;               // block is at most this size,
+constexpr double kTinyBall = 2.0;                   // and below which it is at least this size
+constexpr int kTinyBallBlock = 16384;
 
 inline bm_result *new_result()
 {
