@@ -358,39 +358,69 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
     // a resolve first copies its share of the entries the opening settled
     // (the range pass after it reads them)
     if (CONFLICT && T.chain) settle_copy<RM_THREADS>(*T.chain, lb, launched);
-    const int NGW = max(1, min((na + RM_THREADS - 1) / RM_THREADS, launched / 8));
-    const int chunks = launched / NGW / 8 * 8;
-    if (lb >= NGW * chunks) {                                      // workgroup-uniform
-        range_wg_exit<CONFLICT>(T, clk, smem);
-        return;
-    }
-    const int xcd = lb & 7;
-    const int kk = lb >> 3;
-    const int g = kk % NGW;
-    const int c = (kk / NGW) * 8 + xcd;
-    // the landmark bits of this pass's landmarks (one workgroup per landmark
-    // group sets them; the next block's settle step reads them after the pass)
-    if (!CONFLICT && c == 0 && T.chain && T.chain->settle) {
-        const int aj = g * RM_THREADS + tid;
-        if (aj < na) {
-            const int32_t r = A ? A[aj] : aj;
-            gatomic_or((unsigned long long *)&T.chain->islm[r >> 6], 1ull << (r & 63));
-        }
-    }
-    if (g * RM_WAVES * RM_MP * 32 >= na) {                         // workgroup-uniform
-        range_wg_exit<CONFLICT>(T, clk, smem);
-        return;
-    }
+    // Workgroup -> (landmark group g, tiles [t0, t1)).  A range pass: the
+    // workgroups go to ceil(na / 512) groups times `chunks` point chunks, the
+    // groups of one chunk on one XCD.  A resolve needs, for group g, only the
+    // tiles from 16 g on (candidates past the group's first row): that
+    // triangle is cut into pieces of `per` tiles, so that its longest
+    // workgroup does about the mean work.
+    int g, c = -1, t0, t1;
     const int NT = (int)((n + 31) / 32);
-    const int CT = MT + NT - RT0;                                  // tiles of the point space
-    const int tpc = (CT + chunks - 1) / chunks;
-    const int t0 = c * tpc;
-    const int t1 = min(CT, t0 + tpc);
-    // a resolve needs rows i < j only: no candidate of the chunk lies past
-    // the group's first row, so every word it could write is never read
-    if (t0 >= t1 || (CONFLICT && g * RM_THREADS >= t1 * 32 - 1)) {  // workgroup-uniform
-        range_wg_exit<CONFLICT>(T, clk, smem);
-        return;
+    if constexpr (CONFLICT) {
+        const int ngw = max(1, (na + RM_THREADS - 1) / RM_THREADS);
+        int work = 0;
+        for (int gg = 0; gg < ngw; ++gg) work += max(0, NT - 16 * gg);
+        const int slots = max(1, launched - ngw);
+        const int per = max(1, (work + slots - 1) / slots);
+        g = -1;
+        t0 = t1 = 0;
+        for (int gg = 0, acc = 0; gg < ngw; ++gg) {
+            const int len = max(0, NT - 16 * gg);
+            const int kg = (len + per - 1) / per;
+            if (lb < acc + kg) {
+                g = gg;
+                t0 = 16 * gg + (lb - acc) * per;
+                t1 = min(NT, t0 + per);
+                break;
+            }
+            acc += kg;
+        }
+        if (g < 0 || g * RM_THREADS >= na || t0 >= t1) {           // workgroup-uniform
+            range_wg_exit<CONFLICT>(T, clk, smem);
+            return;
+        }
+    } else {
+        const int NGW = max(1, min((na + RM_THREADS - 1) / RM_THREADS, launched / 8));
+        const int chunks = launched / NGW / 8 * 8;
+        if (lb >= NGW * chunks) {                                  // workgroup-uniform
+            range_wg_exit<CONFLICT>(T, clk, smem);
+            return;
+        }
+        const int xcd = lb & 7;
+        const int kk = lb >> 3;
+        g = kk % NGW;
+        c = (kk / NGW) * 8 + xcd;
+        // the landmark bits of this pass's landmarks (one workgroup per landmark
+        // group sets them; the next block's settle step reads them after the pass)
+        if (c == 0 && T.chain && T.chain->settle) {
+            const int aj = g * RM_THREADS + tid;
+            if (aj < na) {
+                const int32_t r = A ? A[aj] : aj;
+                gatomic_or((unsigned long long *)&T.chain->islm[r >> 6], 1ull << (r & 63));
+            }
+        }
+        if (g * RM_WAVES * RM_MP * 32 >= na) {                     // workgroup-uniform
+            range_wg_exit<CONFLICT>(T, clk, smem);
+            return;
+        }
+        const int CT = MT + NT - RT0;                              // tiles of the point space
+        const int tpc = (CT + chunks - 1) / chunks;
+        t0 = c * tpc;
+        t1 = min(CT, t0 + tpc);
+        if (t0 >= t1) {                                            // workgroup-uniform
+            range_wg_exit<CONFLICT>(T, clk, smem);
+            return;
+        }
     }
     const int pbase = (g * RM_WAVES + wid) * RM_MP;                // first panel of this wave
     const bool live = pbase * 32 < na;                             // wave-uniform
