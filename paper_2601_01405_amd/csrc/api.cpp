@@ -486,7 +486,11 @@ bm_result *run_job(const Job &job, const bm_options &o)
         // -- edges
         const auto t_edges = clk::now();
         int32_t *edges = nullptr;
-        const int64_t E = edges_of(dev, skeys, M, L, n, bn, row_ptr, midx, &edges, nullptr);
+        // Exact greedy: every point lies in some ball, so M >= n, and M == n
+        // means every point lies in exactly one: no two balls meet, no edge.
+        int64_t E = 0;
+        if (!job.fixed && o.refine && M == n) edges = dev.alloc<int32_t>(1);
+        else E = edges_of(dev, skeys, M, L, n, bn, row_ptr, midx, &edges, nullptr);
         dev.sync();
         res->stats.ms_edges = ms_since(t_edges);
 
