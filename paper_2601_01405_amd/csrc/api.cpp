@@ -72,20 +72,21 @@ bm_result *run_job(const Job &job, const bm_options &o)
         double max_nu = 0.0, max_abs = 0.0;
         double *nu = nullptr;
         if (n > 0) {
-            if (o.points_on_device) {
-                int *bad = dev.zeros<int>(1);
-                hip_ok(launch_check_finite(Xd, job.dtype, n * (int64_t)d, bad, dev.s), "check_finite");
-                if (dev.fetch(bad)) fail(BM_ENONFINITE, "a coordinate is NaN or infinite");
-            }
+            // maxima of |x|^2 and |x_k|, and (device points) a non-finite flag,
+            // read back together (one wait); the statistics of a non-finite
+            // input are computed but never used
+            struct Stats3 {
+                unsigned long long v[3];
+            };
+            unsigned long long *st3 = dev.zeros<unsigned long long>(3);
+            if (o.points_on_device)
+                hip_ok(launch_check_finite(Xd, job.dtype, n * (int64_t)d, (int *)(st3 + 2), dev.s), "check_finite");
             nu = dev.alloc<double>((size_t)n);
-            unsigned long long *st2 = dev.zeros<unsigned long long>(2);
-            hip_ok(launch_point_stats(P, nu, st2, dev.s), "point_stats");
-            unsigned long long raw[2];
-            const auto st2h = dev.fetch((const Pair64 *)st2);
-            raw[0] = st2h.v[0];
-            raw[1] = st2h.v[1];
-            std::memcpy(&max_nu, &raw[0], 8);
-            std::memcpy(&max_abs, &raw[1], 8);
+            hip_ok(launch_point_stats(P, nu, st3, dev.s), "point_stats");
+            const Stats3 h = dev.fetch((const Stats3 *)st3);
+            if (h.v[2]) fail(BM_ENONFINITE, "a coordinate is NaN or infinite");
+            std::memcpy(&max_nu, &h.v[0], 8);
+            std::memcpy(&max_abs, &h.v[1], 8);
         }
         MfmaArgs ma{};
         bool ma_ready = false;

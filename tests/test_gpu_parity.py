@@ -206,3 +206,19 @@ def test_range_pair_accounting():
             assert L * (n - L + 1) <= s["range_pairs"] < L * n
         u = bm.build(x, 0.8, path=path, block=128, refine=False)
         assert u.stats["range_pairs"] == u.n_landmarks * n
+
+
+@pytest.mark.parametrize("dtype", ["float32", "float64", "float16"])
+def test_device_points_non_finite(dtype):
+    """Device-resident points with a NaN or an infinity are refused (the flag
+    is read back with the point statistics), and the next build is unaffected."""
+    import torch
+    x = W.clusters(3000, 8, k=4, box=3.0, seed=21, dtype=np.float32)
+    t = torch.from_numpy(x.astype(dtype)).cuda()
+    t[1234, 5] = float("nan") if dtype != "float16" else float("inf")
+    say("device points with a non-finite coordinate", dtype)
+    with pytest.raises(bm.BmError) as ei:
+        bm.build(t, 0.8)
+    assert ei.value.code == bm.BM_ENONFINITE
+    good = torch.from_numpy(x.astype(dtype)).cuda()
+    assert_same(bm.build(good, 0.8), oracle.build(x.astype(dtype), 0.8), f"after the refusal {dtype}")
