@@ -82,3 +82,54 @@ def test_unrefined_within_error_model(case):
     assert oracle.covering_radius(x, L) < eps + delta
     assert oracle.separation(x, L) >= eps - delta
     print(f"    end to end: landmark ratio {e2e.n_landmarks / ref.n_landmarks:.4f}", flush=True)
+
+
+@pytest.mark.parametrize("eps", [13.0, 14.5])
+def test_unrefined_report_gauss128d_full(eps):
+    """The unrefined BF16 oracle at full size (10^6 x 128 Gaussian): membership
+    errors of 256 sampled landmarks against the exact FP64 rows, every error
+    inside the delta band, and the end-to-end net within the Theorem's bounds
+    (every one of 20000 sampled points within eps + delta of a landmark; the
+    separation when the net has at most 40000 landmarks).  Prints the figures
+    of the report."""
+    import torch
+    say = lambda *a: print("[report]", *a, flush=True)
+    x = W.gaussian_128d()
+    n, d = x.shape
+    w = x.astype(np.float64)
+    nu = np.einsum("ij,ij->i", w, w)
+    b = bm.error_bound("bf16", x.dtype, d, eps, nu.max(), np.abs(w).max())
+    delta = b["delta"]
+    say(f"gauss128d eps={eps} delta={delta:.4g}")
+    xd = torch.from_numpy(x).cuda()
+    rng = np.random.default_rng(11)
+    lm = np.sort(rng.choice(n, 256, replace=False)).astype(np.int32)
+    exact = oracle.range_sets(x, lm, eps)
+    approx = bm.range_sets(xd, lm, eps, path="bf16", refine=False)
+    e2 = eps * eps
+    lo2, hi2 = (eps - delta) ** 2 * (1 - 1e-12), (eps + delta) ** 2 * (1 + 1e-12)
+    fn = fp = 0
+    for i in range(lm.shape[0]):
+        e, a = set(exact.row(i).tolist()), set(approx.row(i).tolist())
+        for p in e - a:
+            fn += 1
+            assert lo2 <= oracle.sqdist(x, int(lm[i]), int(p)) < e2
+        for p in a - e:
+            fp += 1
+            assert e2 <= oracle.sqdist(x, int(lm[i]), int(p)) < hi2
+    m = int(exact.member_ptr[-1])
+    say(f"  256 fixed landmarks: {m} exact memberships, FN={fn} FP={fp}, "
+        f"recall={(m - fn) / max(m, 1):.6f} precision={(m - fn) / max(m - fn + fp, 1):.6f}")
+    ref = bm.build(xd, eps)
+    e2e = bm.build(xd, eps, path="bf16", refine=False)
+    L = e2e.landmarks
+    say(f"  end to end: L~/L={e2e.n_landmarks}/{ref.n_landmarks}={e2e.n_landmarks / ref.n_landmarks:.4f} "
+        f"E~/E={e2e.n_edges}/{ref.n_edges}")
+    sample = np.sort(rng.choice(n, 20000, replace=False)).astype(np.int32)
+    first = oracle.first_member(x, L, eps + delta, sample)
+    assert (first >= 0).all()
+    say(f"  all {sample.shape[0]} sampled points within eps + delta of a landmark of the unrefined net")
+    if L.shape[0] <= 40000:
+        s = oracle.separation(x, L)
+        assert s >= eps - delta
+        say(f"  separation s/eps={s / eps:.4f} (>= 1 - delta/eps = {1 - delta / eps:.4f})")
