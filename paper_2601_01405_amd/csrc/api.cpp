@@ -288,7 +288,7 @@ bm_result *run_job(const Job &job, const bm_options &o)
             const int nw = (B + 63) / 64;
             uint64_t *covered = dev.zeros<uint64_t>((size_t)((n + 63) / 64));
             int32_t *cand = dev.alloc<int32_t>((size_t)B);
-            uint64_t *C = dev.alloc<uint64_t>((size_t)B * nw);
+            uint64_t *C = dev.zeros<uint64_t>((size_t)B * nw);      // zero between blocks (the accept clears)
             int *rowflag = dev.alloc<int>((size_t)B);
             // Settled list (refined matrix-core path): landmarks are skipped as
             // points of later range passes, since no landmark is in another's ball.

@@ -210,9 +210,9 @@ void run_batch(const std::vector<const bm_problem *> &probs, const std::vector<i
                 cz.take(np * 4);                                    // settled indices
                 c.i_off = ci.take(t3_floats(q.n) * 4);              // settled thresholds
             }
+            cz.take((size_t)c.B * nw * 8);                          // conflict words (kept zero)
             c.p_off = cp.take(((size_t)q.n * 2 + t3_floats(q.n)) * 4);   // scalars
             cp.take((size_t)c.B * 4);                               // cand
-            cp.take((size_t)c.B * nw * 8);                          // conflict words
             cp.take((size_t)c.B * 4);                               // rowflag
             cp.take((size_t)c.B * 4);                               // A
             cp.take((size_t)q.n * 4);                               // landmarks
@@ -243,9 +243,9 @@ void run_batch(const std::vector<const bm_problem *> &probs, const std::vector<i
             c.sd.idx = (int32_t *)(zero_arena + z.take(np * 4));
             c.sd.T3 = (float *)(inf_arena + i.take(t3_floats(q.n) * 4));
         }
+        c.C = (uint64_t *)(zero_arena + z.take((size_t)c.B * nw * 8));
         float *sc = (float *)(plain_arena + pl.take(((size_t)q.n * 2 + t3_floats(q.n)) * 4));
         c.cand = (int32_t *)(plain_arena + pl.take((size_t)c.B * 4));
-        c.C = (uint64_t *)(plain_arena + pl.take((size_t)c.B * nw * 8));
         c.rowflag = (int32_t *)(plain_arena + pl.take((size_t)c.B * 4));
         c.A = (int32_t *)(plain_arena + pl.take((size_t)c.B * 4));
         c.lm = (int32_t *)(plain_arena + pl.take((size_t)q.n * 4));

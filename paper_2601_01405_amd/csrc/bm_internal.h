@@ -155,7 +155,7 @@ struct ChainTask {
     MfmaArgs a;                     // the chain's operands and scalars
     SettledSet sd;
     const int32_t *perm;            // rank -> original index (null: identity)
-    const uint64_t *C;              // conflict words, ceil(B/64) per candidate
+    uint64_t *C;                    // conflict words, ceil(B/64) per candidate (zero between blocks)
     int32_t *A;                     // accepted ranks of the block
     int32_t *landmarks;             // original indices, selection order
     int32_t *lm_rank;               // ranks, selection order

@@ -261,7 +261,9 @@ __device__ void settle_copy(const ChainTask &T, int part, int parts)
 // takes one flagged row, lane w reading conflict words w, w + 64 (coalesced).
 // The accepted ranks go to A (the range pass's list), the landmark list
 // (original indices) and lm_rank at ordinal st->L, and the block is recorded
-// in blog[(st->blocks - 1) % kBlockLogSize].
+// in blog[(st->blocks - 1) % kBlockLogSize].  The conflict words of the
+// flagged rows are cleared afterwards: the resolve stores only nonzero words
+// (only flagged rows hold any), so the words are all zero between blocks.
 // The acceptance of a block of nc <= RUN * NT candidates.
 template <int NT, int RUN>
 __device__ void accept_run(const ChainTask &T, unsigned char *lds, BM_GLOBAL GreedyState *st, const int nc)
@@ -275,7 +277,7 @@ __device__ void accept_run(const ChainTask &T, unsigned char *lds, BM_GLOBAL Gre
     int16_t *flist = (int16_t *)(tab + MAX_B / 64 + 4);         // [MAX_B] flagged rows
     const int tid = (int)threadIdx.x;
     const int64_t L0 = st->L;
-    const BM_GLOBAL uint64_t *C = gbl(T.C);
+    BM_GLOBAL uint64_t *C = gbl(T.C);
     const int nw = (T.B + 63) / 64;
     const int lane = lane_id(), wid = tid >> 6;
     // Candidate j = k * NT + tid: the 64 lanes of a wave hold 64 consecutive
@@ -355,6 +357,11 @@ __device__ void accept_run(const ChainTask &T, unsigned char *lds, BM_GLOBAL Gre
             if (tid == 0) st->error = 1;
             break;
         }
+    }
+    // back to zero for the next resolve: row j holds words below (j + 63) / 64 only
+    for (int q = wid; q < F; q += NWAVES) {
+        const int j = flist[q];
+        for (int w = lane; w < ((j + 63) >> 6); w += 64) C[(int64_t)j * nw + w] = 0ull;
     }
     // the accepted candidates, compacted in rank order
     uint32_t took = 0;

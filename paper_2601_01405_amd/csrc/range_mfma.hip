@@ -212,9 +212,11 @@ __device__ __forceinline__ int acc_row(int i, int half) { return 8 * (i >> 2) + 
 // mode is the candidate-block resolve: landmarks and points are both the
 // block's candidates (rank A[j] for candidate j, read in place), and the
 // output is C32[j * stride + p] = the bits r of rows i = 32 p + r < j whose
-// ball holds candidate j, for the panels p with 32 p < j (the accept masks or
-// skips the others), plus rowflag[j] = 1 when any bit is set.  Tiles that lie
-// wholly above the diagonal are skipped.
+// ball holds candidate j, for the panels p with 32 p < j, plus rowflag[j] = 1
+// when any bit is set.  The words start at zero and only nonzero ones are
+// stored (the accept clears the rows it read), so a pass over a block with
+// few conflicts writes almost nothing.  Tiles that lie wholly above the
+// diagonal are skipped.
 //
 // Point space of a MEMBERS pass: tiles [0, MT) are the settled list (entries
 // < m valid), then rank tiles from rlo / 32 to the end.  A CONFLICT pass has
@@ -685,21 +687,7 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
                 phit[pi] = !(m <= (a.refine ? tcut - aw[pi] : tcut));
                 hit = hit || phit[pi];
             }
-            if (!__ballot(hit)) {                                        // wave-uniform
-                if (CONFLICT) {
-                    // no pair of the tile conflicts: a zero word for every
-                    // candidate past a panel's first row (the words a row reads;
-                    // the others are masked or never read)
-                    const int64_t p = (int64_t)t * 32 + col;
-#pragma unroll
-                    for (int pi = 0; pi < RM_MP; ++pi) {
-                        const int abase = (pbase + pi) * 32;
-                        if (abase >= na) break;
-                        if (half == 0 && p < n && abase < p) gbl(T.C32)[p * T.c32_stride + (pbase + pi)] = 0u;
-                    }
-                }
-                continue;
-            }
+            if (!__ballot(hit)) continue;                                // wave-uniform (a resolve: words stay zero)
         }
 #pragma unroll
         for (int pi = 0; pi < RM_MP; ++pi) {
@@ -722,16 +710,7 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
                     m = fmaxf(m, av[15]);
                     ph = !(m <= (a.refine ? tcut - aw[pi] : tcut));
                 }
-                if (!__ballot(ph)) {
-                    if (CONFLICT) {
-                        // no pair of the tile conflicts: a zero word for every
-                        // candidate past the panel's first row (the words a row
-                        // reads; the others are masked or never read)
-                        const int64_t p = (int64_t)t * 32 + col;
-                        if (half == 0 && p < n && abase < p) gbl(T.C32)[p * T.c32_stride + (pbase + pi)] = 0u;
-                    }
-                    continue;
-                }
+                if (!__ballot(ph)) continue;                             // (a resolve: words stay zero)
             }
             slow = true;
             const bool stl = t < MT;                                     // wave-uniform
@@ -797,9 +776,9 @@ __global__ __launch_bounds__(RM_THREADS) void k_range_mfma(const RangeTask *__re
                 for (int i = 0; i < 16; ++i)
                     if ((mem >> i) & 1u) w |= 1u << acc_row(i, half);
                 w |= __shfl_xor(w, 32, 64);
-                if (half == 0 && pv && abase < p) {
+                if (w != 0u && half == 0 && pv && abase < p) {
                     gbl(T.C32)[p * T.c32_stride + (pbase + pi)] = w;
-                    if (w) gbl(T.rowflag)[p] = 1;
+                    gbl(T.rowflag)[p] = 1;
                 }
                 continue;
             }
