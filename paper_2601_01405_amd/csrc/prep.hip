@@ -44,13 +44,31 @@ __global__ __launch_bounds__(PS_THREADS) void k_point_stats(PointsView P, double
 {
     __shared__ double sh[2][PS_THREADS / 64];
     double smax = 0.0, mabs = 0.0;
+    // float32 rows of a multiple of 4 coordinates on a 16-byte aligned array are
+    // read 4 at a time (a quarter of the load instructions; the same products
+    // added in the same order)
+    const bool vec4 = DT == 1 && (P.d & 3) == 0 && ((uintptr_t)P.X & 15u) == 0;   // uniform
     for (int64_t r = blockIdx.x * (int64_t)PS_THREADS + threadIdx.x; r < P.n; r += (int64_t)gridDim.x * PS_THREADS) {
         const int64_t o = orig_index(P, r) * (int64_t)P.d;
         double s = 0.0;
-        for (int32_t k = 0; k < P.d; ++k) {
-            double v = load_coord<DT>(P.X, o + k);
-            s = __fma_rn(v, v, s);
-            mabs = fmax(mabs, fabs(v));
+        if (vec4) {
+            const BM_GLOBAL u32x4 *row = (const BM_GLOBAL u32x4 *)((const BM_GLOBAL float *)P.X + o);
+            for (int32_t k4 = 0; k4 < (P.d >> 2); ++k4) {
+                const u32x4 q = row[k4];
+                const double v[4] = {(double)__uint_as_float(q[0]), (double)__uint_as_float(q[1]),
+                                     (double)__uint_as_float(q[2]), (double)__uint_as_float(q[3])};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    s = __fma_rn(v[e], v[e], s);
+                    mabs = fmax(mabs, fabs(v[e]));
+                }
+            }
+        } else {
+            for (int32_t k = 0; k < P.d; ++k) {
+                double v = load_coord<DT>(P.X, o + k);
+                s = __fma_rn(v, v, s);
+                mabs = fmax(mabs, fabs(v));
+            }
         }
         gbl(nu)[r] = s;
         smax = fmax(smax, s);

@@ -58,6 +58,29 @@ __global__ void k_mfma_operands(PointsView P, int kind, int S, double scale, uin
         const int kb = 16 * s + 8 * (lane >> 5);
         uint16_t pv[8], qv[8];
         const int64_t row = p < P.n ? orig_index(P, p) * (int64_t)d : 0;
+        // float32 rows of a multiple of 8 coordinates on a 16-byte aligned array:
+        // the thread's 8 coordinates (one segment of the split) are read as two
+        // float4 loads; the values, and so the operands, are the same
+        float xv[8] = {};
+        const bool vec = DT == 1 && (d & 7) == 0 && ((uintptr_t)P.X & 15u) == 0;   // uniform
+        if (vec && p < P.n) {
+            const int kk0 = kind == MFMA_F16 || kind == MFMA_BF16 ? kb : kb - (kb / d) * d;
+            if ((kind == MFMA_F16 || kind == MFMA_BF16) ? kb < d : kb / d < 3) {
+                const BM_GLOBAL u32x4 *src = (const BM_GLOBAL u32x4 *)((const BM_GLOBAL float *)P.X + row + kk0);
+                const u32x4 u0 = src[0], u1 = src[1];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    xv[e] = __uint_as_float(u0[e]);
+                    xv[4 + e] = __uint_as_float(u1[e]);
+                }
+            }
+        }
+        auto coord = [&](int e, int64_t off) -> double {
+            if constexpr (DT == 1) {
+                if (vec) return (double)xv[e];
+            }
+            return load_coord<DT>(P.X, off);
+        };
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int k = kb + e;
@@ -68,16 +91,16 @@ __global__ void k_mfma_operands(PointsView P, int kind, int S, double scale, uin
                         if constexpr (DT == 2) {
                             a = b = ((const uint16_t *)P.X)[row + k];          // stored float16: exact
                         } else {                                              // exact power-of-two scale,
-                            const float v = (float)(load_coord<DT>(P.X, row + k) * scale);   // then RN to f16
+                            const float v = (float)(coord(e, row + k) * scale);   // then RN to f16
                             a = b = __builtin_bit_cast(uint16_t, (_Float16)v);
                         }
                     }
                 } else if (kind == MFMA_BF16) {
-                    if (k < d) a = b = bf16_rne((float)load_coord<DT>(P.X, row + k));
+                    if (k < d) a = b = bf16_rne((float)coord(e, row + k));
                 } else {   // three-product split: P = [hi|hi|lo], Q = [hi|lo|hi]
                     const int seg = k / d, kk = k - seg * d;
                     if (seg < 3) {
-                        const double x = load_coord<DT>(P.X, row + kk);
+                        const double x = coord(e, row + kk);
                         const uint16_t hi = bf16_rne((float)x);
                         const uint16_t lo = bf16_rne((float)(x - bf16_to_double(hi)));
                         a = (seg == 2) ? lo : hi;
