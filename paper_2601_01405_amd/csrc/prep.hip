@@ -30,9 +30,12 @@ hipError_t launch_check_finite(const void *X, int32_t dtype, int64_t count, int 
 }
 
 // Non-negative doubles order like their bit patterns, so a 64-bit atomicMax keeps the maximum.
+// The slot only grows, so a value not above what it already holds cannot change it: the
+// atomic (serialised with every other one on the address) is skipped then.
 __device__ __forceinline__ void atomic_max_nonneg(unsigned long long *slot, double v)
 {
-    atomicMax(slot, (unsigned long long)__double_as_longlong(v));
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    if (b > __hip_atomic_load(gbl(slot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(slot, b);
 }
 
 // Grid-stride over the points; the maxima are reduced per workgroup first, so
