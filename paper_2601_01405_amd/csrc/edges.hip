@@ -97,37 +97,14 @@ __global__ void k_flag_rows(const uint64_t *keys, int64_t M, int32_t bn, const i
     }
 }
 
-// The flagged rows, in no particular order: list[0 .. *count).  A workgroup
-// takes LR_THREADS * LR_PER consecutive flags (thread t reads t, t +
-// LR_THREADS, ...: coalesced), scans its counts and reserves its slots with
-// one atomic, so the counter sees one atomic per 4096 flags instead of one per
-// wave (those serialise on the single address).
-constexpr int LR_THREADS = 256, LR_PER = 16;
-__global__ __launch_bounds__(LR_THREADS) void k_list_rows(const int *flag, int64_t L, int32_t *list,
-                                                          unsigned long long *count)
+// The flagged rows, in no particular order: list[0 .. *count).
+__global__ void k_list_rows(const int *flag, int64_t L, int32_t *list, unsigned long long *count)
 {
-    __shared__ int sh[LR_THREADS / 64];
-    __shared__ unsigned long long base;
-    const int tid = (int)threadIdx.x;
-    constexpr int64_t span = (int64_t)LR_THREADS * LR_PER;
-    for (int64_t b0 = (int64_t)blockIdx.x * span; b0 < L; b0 += (int64_t)gridDim.x * span) {   // uniform
-        uint32_t want = 0;
-#pragma unroll
-        for (int k = 0; k < LR_PER; ++k) {
-            const int64_t i = b0 + (int64_t)k * LR_THREADS + tid;
-            if (i < L && flag[i] != 0) want |= 1u << k;
-        }
-        int total = 0;
-        int pos = block_excl_scan<LR_THREADS>((int)__popc(want), &total, sh);
-        if (tid == 0 && total > 0) base = atomicAdd(count, (unsigned long long)total);
-        __syncthreads();
-        const unsigned long long b = base;
-        while (want) {
-            const int k = __builtin_ctz(want);
-            want &= want - 1;
-            list[b + (unsigned long long)pos++] = (int32_t)(b0 + (int64_t)k * LR_THREADS + tid);
-        }
-        __syncthreads();                                         // base is set again next round
+    for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x; i0 < L; i0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = i0 + threadIdx.x;
+        const bool want = i < L && flag[i] != 0;
+        const unsigned long long pos = wave_append(count, want);
+        if (want) list[pos] = (int32_t)i;
     }
 }
 
@@ -140,9 +117,9 @@ hipError_t launch_edge_rows(const uint64_t *keys, int64_t M, int32_t bn, const i
     if (M > 0) k_flag_rows<<<(int)blocks, 256, 0, s>>>(keys, M, bn, sptr, flag);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    blocks = (L + LR_THREADS * LR_PER - 1) / (LR_THREADS * LR_PER);
-    if (blocks > 4096) blocks = 4096;
-    k_list_rows<<<(int)blocks, LR_THREADS, 0, s>>>(flag, L, list, count);
+    blocks = (L + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    k_list_rows<<<(int)blocks, 256, 0, s>>>(flag, L, list, count);
     return hipGetLastError();
 }
 
