@@ -23,6 +23,7 @@ PEAK_BF16_TFLOPS = 2500.0       # MI355X dense bf16 matrix peak
 PEAK_F16_TFLOPS = 2500.0
 PEAK_FP32_VALU_TFLOPS = 157.3
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "range_mfma_clusters16d_n200k_traffic.txt")
+TRAFFIC_WORKLOAD = "clusters16d_n200k_f32"     # the workload those counters were taken on
 KERNEL_SRC = os.path.join(ROOT, "paper_2601_01405_amd", "csrc", "range_mfma.hip")
 
 
@@ -237,8 +238,10 @@ def summarize_trace(db, out, command):
     print("\n".join(lines))
 
 
-def range_roofline(runs, d, used_path, steps):
-    """Roofline entry of the range pass from profiled runs (device-clock windows)."""
+def range_roofline(runs, d, used_path, steps, workload):
+    """Roofline entry of the range pass from profiled runs (device-clock windows).
+    The HBM traffic comes from counters taken on one workload; other workloads
+    report none."""
     range_ms = sum(s["ms_range_kernel"] for run in runs for s in run)
     launches = sum(s["range_launches"] for run in runs for s in run)
     range_pairs = sum(s["range_pairs"] for run in runs for s in run)
@@ -247,7 +250,7 @@ def range_roofline(runs, d, used_path, steps):
     peak = PEAK_F16_TFLOPS if used_path == "f16" else PEAK_BF16_TFLOPS
     return {"bound": "mfma", "kernel": "k_range_mfma", "achieved": achieved, "peak": peak,
             "unit": "TFLOP/s", "frac": (achieved / peak) if achieved else None,
-            "traffic": read_traffic(range_pairs / max(launches, 1)),
+            "traffic": read_traffic(range_pairs / max(launches, 1)) if workload == TRAFFIC_WORKLOAD else None,
             "per_launch_ms": range_ms / max(launches, 1),
             "launches_per_step": launches / steps,
             "flops_per_pair": 2 * d, "pairs_per_launch": range_pairs / max(launches, 1),
@@ -412,7 +415,7 @@ def main():
     pruns = [step(args.path, profile=True) for _ in range(args.steps)]
     torch.cuda.synchronize()
     prof_ms = (time.perf_counter() - t0) / args.steps * 1e3
-    roofline = range_roofline(pruns, d, used_path, args.steps)
+    roofline = range_roofline(pruns, d, used_path, args.steps, args.workload)
     log(f"profiled repeat: {prof_ms:.2f} ms/step, range passes {roofline['per_launch_ms'] * 1e3:.1f} us/launch, "
         f"{roofline['achieved']:.1f} TFLOP/s algorithmic")
 
