@@ -33,6 +33,10 @@ MUTANTS = {
     "float_threshold": ("const double e2 = eps * eps;   /* RN(eps^2), computed once */",
                         "const double e2 = (float)(eps * eps);"),
     "fused_multiply_add": None,   # source unchanged, built with contraction on
+    "first_member_takes_last": ("for (int64_t i = 0; i < L && f < 0; ++i)", "for (int64_t i = 0; i < L; ++i)"),
+    "covering_takes_min": ("if (best > worst) worst = best;", "if (best < worst) worst = best;"),
+    "separation_skips_neighbours": ("for (int64_t j = i + 1; j < L; ++j) {\n            double s2 = sqdist_w(w + (int64_t)landmarks[i] * d",
+                                    "for (int64_t j = i + 2; j < L; ++j) {\n            double s2 = sqdist_w(w + (int64_t)landmarks[i] * d"),
 }
 
 
@@ -44,6 +48,8 @@ def quick_pins():
     yield "certificate", lambda: pins.test_certificate_random(1)
     yield "knn", pins.test_knn_eps_closed_form
     yield "threshold", pins.test_threshold_is_rounded_in_double
+    yield "net", pins.test_net_measures_hand_computed
+    yield "first", pins.test_first_member_hand_computed
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))

@@ -289,3 +289,33 @@ def test_first_member_matches_all_pairs_predicate():
     for q in range(400):
         hits = np.nonzero(mem[res.landmarks, q])[0]
         assert got[q] == (hits[0] if hits.size else -1)
+
+
+def test_net_measures_hand_computed():
+    """Covering radius (largest distance from a point to its nearest landmark)
+    and separation (smallest distance between two landmarks) of the Theorem in
+    Sec. 5.1, by hand: on the line 0..9 with landmarks at 0 and 5 the farthest
+    point is 9 (4 from 5); with landmarks 0, 4, 9 every point is within 2 and
+    the closest landmarks are 0 and 4.  In the plane, (0,0), (3,4), (6,8),
+    (3,0) with landmarks (0,0) and (6,8): (3,4) is 5 from both, (3,0) is 3 from
+    (0,0), and the landmarks are 10 apart (3-4-5 triangles)."""
+    line = np.arange(10, dtype=np.float64)[:, None]
+    assert oracle.covering_radius(line, [0, 5]) == 4.0
+    assert oracle.separation(line, [0, 5]) == 5.0
+    assert oracle.covering_radius(line, [0, 4, 9]) == 2.0
+    assert oracle.separation(line, [0, 4, 9]) == 4.0
+    plane = np.array([[0.0, 0.0], [3.0, 4.0], [6.0, 8.0], [3.0, 0.0]])
+    assert oracle.covering_radius(plane, [0, 2]) == 5.0
+    assert oracle.separation(plane, [0, 2]) == 10.0
+    assert oracle.separation(plane, [1]) == math.inf       # one landmark: no pair
+
+
+def test_first_member_hand_computed():
+    """First landmark (selection position) whose open ball of radius 2.5 holds
+    each query, on the line 0..9 with landmarks 0 then 4: 2 is 2 from both (the
+    first, position 0, wins); 3 is 3 from 0 but 1 from 4; 8 is 4 from 4 and in
+    no ball; 1 is 1 from 0 only.  With the landmarks listed as 4 then 0, the
+    shared query 2 goes to 4 (now position 0)."""
+    line = np.arange(10, dtype=np.float64)[:, None]
+    assert oracle.first_member(line, [0, 4], 2.5, [2, 3, 8, 1]).tolist() == [0, 1, -1, 0]
+    assert oracle.first_member(line, [4, 0], 2.5, [2, 3, 8, 1]).tolist() == [0, 0, -1, 1]
